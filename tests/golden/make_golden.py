@@ -1,0 +1,61 @@
+"""Write the stored oracle results used by the parity tests.
+
+Calls only the seeded instance generator and the CPU oracle (``oracle/``);
+nothing here touches the GPU library.  Run from the repository root:
+
+    python tests/golden/make_golden.py c1_walk40 c2_md30_38
+
+Each ``<workload>.json`` holds, per instance, the start state (hex nibbles),
+the optimal length, the f-limits and the nodes expanded under each limit with
+the final limit run to completion.
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from oracle import oracle  # noqa: E402
+from paper_1705_02843_amd import instances  # noqa: E402
+
+SPECS = {
+    "c1_walk40": (lambda: instances.c1_walk40(), 4),
+    "c2_md30_38": (lambda: instances.c2_md30_38(), 4),
+    "c3_uneven_first512": (lambda: tuple(x[:512] for x in instances.c3_uneven()), 4),
+}
+
+
+def write(name: str, nthreads: int) -> None:
+    make, width = SPECS[name]
+    states, walk = make()
+    t0 = time.time()
+    r = oracle.solve(states, width, nthreads=nthreads)
+    dt = time.time() - t0
+    assert r.rc == 0, r.rc
+    recs = []
+    for i in range(states.shape[0]):
+        k = int(r.niter[i])
+        recs.append({
+            "state": "".join("%x" % v if width <= 4 else "%02x" % v for v in states[i]),
+            "walk": int(walk[i]),
+            "length": int(r.length[i]),
+            "limits": [int(x) for x in r.limits[i, :k]],
+            "nodes": [int(x) for x in r.nodes[i, :k]],
+        })
+    out = {"workload": name, "width": width, "n": int(states.shape[0]),
+           "total_nodes": int(sum(sum(x["nodes"]) for x in recs)),
+           "oracle_seconds": round(dt, 1), "oracle_threads": nthreads, "instances": recs}
+    with open(os.path.join(HERE, name + ".json"), "w") as f:
+        json.dump(out, f, indent=0, separators=(",", ":"))
+    print(name, out["total_nodes"], "nodes", round(dt, 1), "s")
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or list(SPECS)
+    for nm in names:
+        write(nm, os.cpu_count() or 1)

@@ -1,0 +1,207 @@
+"""Pins of the CPU oracle to facts that do not come from the oracle itself.
+
+* exhaustive breadth-first search over all 3x3 states (shortest lengths,
+  reachable set = parity-invariant set);
+* 4x4 breadth-first search to a bounded depth (shortest lengths);
+* a layered path-count recurrence (per-f-limit node counts);
+* closed forms (goal, one move from the goal);
+* the heuristic's admissibility, parity and unit change per move;
+* f-limits that rise by exactly 2 (parity + consistency of Manhattan).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import puzzle_ref as P
+from oracle import oracle
+from paper_1705_02843_amd import instances as I
+
+
+@pytest.fixture(scope="module")
+def bfs3():
+    return P.bfs_distances(3)
+
+
+def _solve(states, w, **kw):
+    r = oracle.solve(P.as_array(states), w, nthreads=8, **kw)
+    return r
+
+
+# ---- closed forms ---------------------------------------------------------
+
+@pytest.mark.parametrize("w", [2, 3, 4, 5])
+def test_goal_is_length_zero_one_node(w):
+    r = _solve([P.goal(w)], w)
+    assert r.rc == 0
+    assert r.length[0] == 0
+    assert r.niter[0] == 1 and r.limits[0, 0] == 0
+    assert r.nodes[0, 0] == 1 and r.nodes[0, 1:].sum() == 0
+
+
+@pytest.mark.parametrize("w", [3, 4, 5])
+def test_one_move_from_goal(w):
+    # the blank starts at 0: only R and D apply
+    for a in (2, 3):
+        s = P.random_state_at(w, [a])
+        r = _solve([s], w)
+        assert r.rc == 0 and r.length[0] == 1
+        # start expanded, then the goal child (f = 1); the other children
+        # have f = 3 and are pruned; the goal's children have f = 3
+        assert list(r.nodes[0, :2]) == [2, 0]
+        assert r.limits[0, 0] == 1
+
+
+# ---- exhaustive 3x3 -------------------------------------------------------
+
+def test_3x3_reachable_set_is_parity_invariant_set(bfs3):
+    assert len(bfs3) == math.factorial(9) // 2 == 181440
+    n_ok = 0
+    for perm in itertools.permutations(range(9)):
+        b = perm.index(0)
+        inv = P.inversion_parity(perm)
+        solvable = inv == ((b // 3 + b % 3) & 1)
+        assert solvable == (perm in bfs3)
+        n_ok += solvable
+        # the oracle's own solvability test agrees on every permutation
+    assert n_ok == 181440
+
+
+def test_3x3_oracle_check_state_agrees(bfs3):
+    for k, perm in enumerate(itertools.permutations(range(9))):
+        if k % 7:  # a fixed 1/7 sample keeps this under a few seconds
+            continue
+        rc = oracle.check_state(np.array(perm, np.uint8), 3)
+        assert rc == (0 if perm in bfs3 else oracle.EUNSOLVABLE)
+
+
+def test_3x3_lengths_equal_bfs_for_every_state(bfs3):
+    states = list(bfs3.keys())
+    r = _solve(states, 3)
+    assert r.rc == 0
+    want = np.array([bfs3[s] for s in states], np.int32)
+    np.testing.assert_array_equal(r.length, want)
+
+
+def test_3x3_manhattan_admissible_parity_consistent(bfs3):
+    for s, d in bfs3.items():
+        h = oracle.manhattan(np.array(s, np.uint8), 3)
+        assert h == P.manhattan(s, 3)
+        assert h <= d and (d - h) % 2 == 0
+        for _, c in P.neighbours(s, 3):
+            assert abs(P.manhattan(c, 3) - h) == 1
+    assert oracle.manhattan(np.arange(9, dtype=np.uint8), 3) == 0
+
+
+def test_blank_must_be_excluded_from_heuristic():
+    # with the blank counted, a state one move from the goal would score 2 > 1
+    s = P.random_state_at(4, [2])
+    assert oracle.manhattan(np.array(s, np.uint8), 4) == 1
+
+
+def test_3x3_counts_equal_layer_recurrence(bfs3):
+    rng = np.random.default_rng(11)
+    states = list(bfs3.keys())
+    pick = [states[i] for i in rng.choice(len(states), 60, replace=False)]
+    pick.append(max(bfs3, key=bfs3.get))  # a deepest state (31 moves)
+    r = _solve(pick, 3)
+    assert r.rc == 0
+    for i, s in enumerate(pick):
+        for j in range(r.niter[i]):
+            L = int(r.limits[i, j])
+            assert int(r.nodes[i, j]) == P.layered_path_count(s, 3, L), (s, L)
+
+
+def test_limits_rise_by_two_and_end_at_optimum(bfs3):
+    states = list(bfs3.keys())[::97]
+    r = _solve(states, 3)
+    for i, s in enumerate(states):
+        h0 = P.manhattan(s, 3)
+        k = r.niter[i]
+        assert r.limits[i, 0] == h0
+        assert list(r.limits[i, :k]) == [h0 + 2 * j for j in range(k)]
+        assert r.limits[i, k - 1] == bfs3[s] == r.length[i]
+
+
+# ---- 4x4 ------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def bfs4():
+    return P.bfs_distances(4, max_depth=15)
+
+
+def test_4x4_lengths_equal_bounded_bfs(bfs4):
+    rng = np.random.default_rng(5)
+    by_depth = {}
+    for s, d in bfs4.items():
+        by_depth.setdefault(d, []).append(s)
+    pick = []
+    for d in sorted(by_depth):
+        lst = by_depth[d]
+        for i in rng.choice(len(lst), min(len(lst), 25), replace=False):
+            pick.append(lst[i])
+    r = _solve(pick, 4)
+    assert r.rc == 0
+    np.testing.assert_array_equal(r.length, [bfs4[s] for s in pick])
+
+
+def test_4x4_counts_equal_layer_recurrence():
+    rng = np.random.default_rng(3)
+    picks = []
+    for n_moves in (6, 10, 14, 18, 22, 26):
+        s, _ = I.random_walk(rng, 4, n_moves)
+        picks.append(tuple(int(x) for x in s))
+    r = _solve(picks, 4)
+    assert r.rc == 0
+    for i, s in enumerate(picks):
+        for j in range(r.niter[i]):
+            L = int(r.limits[i, j])
+            assert int(r.nodes[i, j]) == P.layered_path_count(s, 4, L)
+
+
+def test_4x4_walk_bounds_and_check_mode():
+    s, lens = I.c1_walk40(n=16)
+    r = oracle.solve(s, 4, nthreads=8, check=True)
+    assert r.rc == 0
+    h0 = np.array([oracle.manhattan(x, 4) for x in s])
+    assert (r.length <= lens).all() and ((lens - r.length) % 2 == 0).all()
+    assert (r.length >= h0).all()
+    for i in range(len(s)):
+        k = r.niter[i]
+        assert list(r.limits[i, :k]) == [h0[i] + 2 * j for j in range(k)]
+        # each f-limited iteration repeats (at least) all of the previous one
+        assert all(r.nodes[i, j + 1] > r.nodes[i, j] for j in range(k - 1))
+
+
+@pytest.mark.parametrize("w", [3, 5])
+def test_other_widths_walk_bounds(w):
+    rng = np.random.default_rng(w)
+    states = [I.random_walk(rng, w, 24)[0] for _ in range(8)]
+    r = oracle.solve(np.stack(states), w, nthreads=8, check=True)
+    assert r.rc == 0
+    assert (r.length <= 24).all() and ((24 - r.length) % 2 == 0).all()
+
+
+# ---- rejected inputs ------------------------------------------------------
+
+def test_rejects_non_permutation_and_wrong_parity():
+    g = np.arange(16, dtype=np.uint8)
+    bad = g.copy(); bad[3] = 5
+    swapped = g.copy(); swapped[1], swapped[2] = swapped[2], swapped[1]
+    assert oracle.check_state(bad, 4) == oracle.EINVAL
+    assert oracle.check_state(swapped, 4) == oracle.EUNSOLVABLE
+    r = oracle.solve(np.stack([g, swapped, bad]), 4)
+    assert list(r.status) == [0, oracle.EUNSOLVABLE, oracle.EINVAL]
+    assert list(r.length) == [0, -1, -1]
+    assert r.rc == oracle.EUNSOLVABLE
+
+
+def test_limit_cap():
+    s, _ = I.c1_walk40(n=1)
+    h0 = oracle.manhattan(s[0], 4)
+    r = oracle.solve(s, 4, max_limit=h0)
+    full = oracle.solve(s, 4)
+    if full.length[0] > h0:
+        assert r.rc == oracle.ELIMIT
+        assert r.nodes[0, 0] == full.nodes[0, 0]
