@@ -32,6 +32,7 @@ def neighbours(state: tuple, w: int):
 def manhattan(state, w: int) -> int:
     h = 0
     for p, t in enumerate(state):
+        t = int(t)
         if t:
             h += abs(p // w - t // w) + abs(p % w - t % w)
     return h
