@@ -1,0 +1,127 @@
+/*
+ * bpida.h -- Block-Parallel IDA* on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Horie & Fukunaga, "Block-Parallel IDA* for GPUs" (SoCS 2017),
+ * Alg. 1 (BPIDA* and BPDFS) with the all-optimal-solutions completion of the
+ * final f-limited iteration (Sec. 6.1).  The domain is the sliding-tile
+ * puzzle with the Manhattan distance heuristic (Sec. 1, Sec. 3).  All search
+ * work runs in HIP kernels: ingest (validate, pack, h), root split
+ * (CreateRootSet), the block-parallel f-limited DFS (BPDFS: one subtree per
+ * workgroup, the DFS stack in LDS, one wavefront expanding 16 nodes x 4 moves
+ * per round) and the per-limit reduction of node counts and next limits.
+ *
+ * Conventions shared by every entry point:
+ *   - a state is width*width bytes, row-major; byte p is the tile at cell p,
+ *     0 is the blank; the goal holds tile p at cell p;
+ *   - moves are blank moves U, L, R, D, unit cost; a move that undoes the
+ *     one that produced a node is not generated (parent pruning);
+ *   - h = Manhattan distance of the non-blank tiles;
+ *   - the f-limits are h0, h0+2, ... (Manhattan changes by exactly 1 per
+ *     move and keeps the parity of the path length, so no other limit can
+ *     occur); the final limit, the optimal length, is searched to completion
+ *     so that every count is unique.
+ *
+ * Thread safety: calls may come from several host threads; they are
+ * serialised inside the library (one shared device workspace per device).
+ * Errors never abort and no C++ exception crosses this interface.
+ */
+#ifndef BPIDA_H
+#define BPIDA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Columns of the per-limit node-count matrix: limit h0 + 2j goes in column j. */
+#define BPIDA_MAX_THRESHOLDS 64
+
+/* Widths supported by the search kernels. */
+#define BPIDA_MIN_WIDTH 4
+#define BPIDA_MAX_WIDTH 4
+
+enum bpida_status {
+  BPIDA_OK = 0,
+  BPIDA_EINVAL = -1,      /* bad argument, or a state that is not a permutation */
+  BPIDA_EUNSOLVABLE = -2, /* permutation parity and blank parity disagree       */
+  BPIDA_ELIMIT = -3,      /* more than BPIDA_MAX_THRESHOLDS limits, or past the
+                             max_threshold option; counts of the limits that
+                             were completed are kept                            */
+  BPIDA_ENOMEM = -4,      /* device allocation failed, or a per-workgroup spill
+                             area overflowed                                    */
+  BPIDA_EDEVICE = -5,     /* no usable gfx950 device, or a HIP call failed      */
+  BPIDA_EINTERNAL = -6,   /* a consistency check failed (next limit != L + 2)   */
+};
+
+/*
+ * Solve n_instances puzzles given in host memory (BPIDA*, Alg. 1).
+ *
+ * states     host, n_instances * width * width bytes (layout above).
+ * width      side of the board; 4 (the 15-puzzle).
+ * out_len    host, n_instances int32: optimal solution length, or -1 for an
+ *            instance that is invalid, unsolvable or stopped by a limit.
+ * out_nodes_per_threshold
+ *            host, n_instances * BPIDA_MAX_THRESHOLDS uint64, row-major:
+ *            [i][j] = nodes expanded by the f-limited iteration with limit
+ *            h0(i) + 2j (start, interior and goal nodes included); columns
+ *            past instance i's last completed limit are 0.
+ * Returns BPIDA_OK if every instance was solved, otherwise the first negative
+ * code met in instance order; the other instances are still solved.  Argument
+ * errors (null pointers, n_instances < 0, unsupported width) are reported
+ * before any device work and leave the outputs untouched.  Synchronous.  The
+ * caller owns all buffers; nothing is retained after return.
+ */
+int bpida_solve(const uint8_t *states, int32_t n_instances, int32_t width, int32_t *out_len,
+                uint64_t *out_nodes_per_threshold);
+
+/*
+ * As bpida_solve, with every buffer in device memory of the current device:
+ * d_states (n * width * width bytes), d_len (n int32), d_nodes
+ * (n * BPIDA_MAX_THRESHOLDS uint64).  Validation runs on the device; the
+ * per-instance status is written to d_len (-1) and the return value is the
+ * first failing code.  Work is ordered on `hip_stream` (a hipStream_t, NULL =
+ * the null stream); the call returns after the results are in d_len and
+ * d_nodes (the limit loop reads 16 bytes per limit back to the host).
+ */
+int bpida_solve_device(const uint8_t *d_states, int32_t n_instances, int32_t width,
+                       int32_t *d_len, uint64_t *d_nodes, void *hip_stream);
+
+/*
+ * Set a tuning or control option for subsequent calls (process-wide).
+ *   "frontier_depth"     depth D of the root split, 0..16 (default 10)
+ *   "lds_stack_capacity" DFS stack entries per workgroup in LDS: 128, 256,
+ *                        512 or 1024 (default 512); deeper entries spill
+ *   "spill_capacity"     per-workgroup HBM spill entries, a multiple of 64
+ *                        (default 16384)
+ *   "max_workgroups"     cap on the persistent search grid (0 = occupancy)
+ *   "max_threshold"      stop with BPIDA_ELIMIT before a limit above this
+ *                        (-1 = none, default)
+ * Returns BPIDA_OK, or BPIDA_EINVAL for an unknown key or a bad value.
+ */
+int bpida_set_option(const char *key, int64_t value);
+
+/* Current value of an option, or INT64_MIN for an unknown key. */
+int64_t bpida_get_option(const char *key);
+
+/*
+ * Statistics of the last completed solve call on this process:
+ *   out[0] search rounds (pop-expand-push cycles, the repetitions of BPDFS's
+ *          loop), summed over workgroups and limits
+ *   out[1] nodes expanded by the search kernel (interior split nodes excluded)
+ *   out[2] entries spilled from LDS to HBM
+ *   out[3] search-kernel launches
+ *   out[4] search-kernel time in microseconds (device events, summed)
+ *   out[5] largest per-workgroup spill stack seen, in entries
+ * n = number of slots to fill (<= 8).  Returns BPIDA_OK or BPIDA_EINVAL.
+ */
+int bpida_last_stats(uint64_t *out, int32_t n);
+
+/* Static, human-readable text for a status code. */
+const char *bpida_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BPIDA_H */

@@ -1,0 +1,116 @@
+"""ctypes binding of ``libbpida.so`` (the C ABI declared in ``include/bpida.h``).
+
+Argument marshalling only: every step of the search runs in the library's HIP
+kernels.  Importing this module loads the library and raises if it has not
+been built; there is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+MAX_THRESHOLDS = 64
+OK, EINVAL, EUNSOLVABLE, ELIMIT, ENOMEM, EDEVICE, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbpida.so")
+
+EXPORTS = ("bpida_solve", "bpida_solve_device", "bpida_set_option", "bpida_get_option",
+           "bpida_last_stats", "bpida_strerror")
+
+
+class BpidaError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what or "bpida", strerror(code), code))
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libbpida.so is not built; run `python -m paper_1705_02843_amd.build` "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    lib.bpida_solve.argtypes = [P(ctypes.c_uint8), ctypes.c_int32, ctypes.c_int32,
+                                P(ctypes.c_int32), P(ctypes.c_uint64)]
+    lib.bpida_solve.restype = ctypes.c_int
+    lib.bpida_solve_device.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.bpida_solve_device.restype = ctypes.c_int
+    lib.bpida_set_option.argtypes = [ctypes.c_char_p, ctypes.c_int64]
+    lib.bpida_set_option.restype = ctypes.c_int
+    lib.bpida_get_option.argtypes = [ctypes.c_char_p]
+    lib.bpida_get_option.restype = ctypes.c_int64
+    lib.bpida_last_stats.argtypes = [P(ctypes.c_uint64), ctypes.c_int32]
+    lib.bpida_last_stats.restype = ctypes.c_int
+    lib.bpida_strerror.argtypes = [ctypes.c_int]
+    lib.bpida_strerror.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def strerror(code: int) -> str:
+    return lib.bpida_strerror(int(code)).decode()
+
+
+def set_option(key: str, value: int) -> None:
+    rc = lib.bpida_set_option(key.encode(), int(value))
+    if rc != OK:
+        raise BpidaError(rc, "set_option(%s=%r)" % (key, value))
+
+
+def get_option(key: str) -> int:
+    return int(lib.bpida_get_option(key.encode()))
+
+
+def last_stats() -> dict:
+    out = (ctypes.c_uint64 * 8)()
+    rc = lib.bpida_last_stats(out, 8)
+    if rc != OK:
+        raise BpidaError(rc, "last_stats")
+    keys = ("rounds", "search_nodes", "spilled", "launches", "search_us", "spill_high_water")
+    return {k: int(out[i]) for i, k in enumerate(keys)}
+
+
+def solve_raw(states: np.ndarray, width: int = 4):
+    """Host-buffer entry point.  Returns (rc, out_len int32[n], nodes uint64[n, 64])."""
+    st = np.ascontiguousarray(np.asarray(states, dtype=np.uint8).reshape(-1, width * width))
+    n = st.shape[0]
+    out_len = np.full(n, -7, np.int32)
+    nodes = np.zeros((n, MAX_THRESHOLDS), np.uint64)
+    rc = lib.bpida_solve(st.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), n, width,
+                         out_len.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    return int(rc), out_len, nodes
+
+
+def solve(states, width: int = 4):
+    """Solve a batch given as a numpy array; raises BpidaError on failure."""
+    rc, out_len, nodes = solve_raw(states, width)
+    if rc != OK:
+        raise BpidaError(rc, "bpida_solve")
+    return out_len, nodes
+
+
+def solve_device(d_states, d_len, d_nodes, width: int = 4, stream=None) -> int:
+    """Device-buffer entry point on torch tensors (uint8 [n, w*w], int32 [n],
+    int64/uint64 [n, 64]) of the current device.  ``stream`` is a
+    ``torch.cuda.Stream`` (default: torch's current stream).  Returns the
+    status code."""
+    import torch  # device buffers and streams only
+
+    n = int(d_states.shape[0])
+    assert d_states.is_cuda and d_states.dtype == torch.uint8 and d_states.is_contiguous()
+    assert d_states.numel() == n * width * width
+    assert d_len.is_cuda and d_len.dtype == torch.int32 and d_len.numel() >= n
+    assert d_nodes.is_cuda and d_nodes.dtype in (torch.int64, torch.uint64)
+    assert d_nodes.is_contiguous() and d_nodes.numel() >= n * MAX_THRESHOLDS
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(lib.bpida_solve_device(ctypes.c_void_p(d_states.data_ptr()), n, width,
+                                      ctypes.c_void_p(d_len.data_ptr()),
+                                      ctypes.c_void_p(d_nodes.data_ptr()),
+                                      ctypes.c_void_p(s.cuda_stream)))

@@ -1,0 +1,373 @@
+// bpida_host.hip -- C ABI and host driver of Block-Parallel IDA* (Alg. 1).
+//
+// The host side does what Alg. 1's BPIDA* function does on the CPU: it
+// launches the root split once (CreateRootSet), starts at limit h0
+// (DecideFirstLimit) and repeats one search launch per f-limit, one subtree
+// per workgroup (parallelForByBlocks), reading back 48 bytes per limit to
+// decide whether to stop.  Every node expansion, count and minimum is
+// computed by the kernels in bpida_kernels.hip.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bpida.h"
+#include "bpida_internal.h"
+
+namespace bpida {
+namespace {
+
+struct Options {
+  int64_t frontier_depth = 10;
+  int64_t lds_stack_capacity = 512;
+  int64_t spill_capacity = 16384;
+  int64_t max_workgroups = 0;
+  int64_t max_threshold = -1;
+};
+
+std::mutex g_mu;  // serialises solves and option changes
+Options g_opt;
+uint64_t g_stats[8] = {0};
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t want) {
+    if (want <= bytes) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      if (e != hipSuccess) return e;
+      p = nullptr;
+      bytes = 0;
+    }
+    size_t b = std::max<size_t>(want, 256);
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return e;
+    }
+    bytes = b;
+    return hipSuccess;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+struct Workspace {
+  int device = -1;
+  int num_cu = 0;
+  bool arch_ok = false;
+  DevBuf inst, tree, tree_off, level_cnt, hist, goal_g, err, cursor, part, spill_t, spill_m, res;
+  DevBuf h2d_states, out_len, out_nodes;
+  LimitResult* h_res = nullptr;  // pinned
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+Workspace g_ws;
+
+int map_err(hipError_t e) {
+  if (e == hipSuccess) return BPIDA_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return BPIDA_ENOMEM;
+  return BPIDA_EDEVICE;
+}
+
+int ensure_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return BPIDA_EDEVICE;
+  }
+  if (g_ws.device == dev) return g_ws.arch_ok ? BPIDA_OK : BPIDA_EDEVICE;
+  if (g_ws.device >= 0) return BPIDA_EDEVICE;  // one device per process
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return BPIDA_EDEVICE;
+  }
+  g_ws.device = dev;
+  g_ws.num_cu = prop.multiProcessorCount;
+  g_ws.arch_ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+  if (!g_ws.arch_ok) return BPIDA_EDEVICE;
+  if (hipHostMalloc((void**)&g_ws.h_res, sizeof(LimitResult), hipHostMallocDefault) != hipSuccess)
+    return BPIDA_ENOMEM;
+  if (hipEventCreate(&g_ws.ev0) != hipSuccess || hipEventCreate(&g_ws.ev1) != hipSuccess)
+    return BPIDA_EDEVICE;
+  return BPIDA_OK;
+}
+
+// Number of non-backtracking blank walks of each length 0..depth from `blank`
+// (the exact size of each level of the split tree).
+void level_sizes(int blank, int depth, int32_t* out) {
+  int64_t cur[16][5] = {};
+  cur[blank][4] = 1;
+  for (int d = 0; d <= depth; ++d) {
+    int64_t tot = 0, nxt[16][5] = {};
+    for (int c = 0; c < 16; ++c)
+      for (int fb = 0; fb < 5; ++fb) {
+        const int64_t m = cur[c][fb];
+        if (!m) continue;
+        tot += m;
+        for (int a = 0; a < 4; ++a) {
+          if (!((kMoveMask4 >> (4 * c + a)) & 1ull) || a == fb) continue;
+          const int n = c + (a == 0 ? -4 : a == 1 ? -1 : a == 2 ? 1 : 4);
+          nxt[n][3 - a] += m;
+        }
+      }
+    out[d] = (int32_t)tot;
+    memcpy(cur, nxt, sizeof cur);
+  }
+}
+
+// The plain BPIDA* driver.  All buffers are device buffers; outputs are
+// written on `st`.
+int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes, hipStream_t st,
+              const Options& O) {
+  Workspace& W = g_ws;
+  uint64_t stats[8] = {0};
+  hipError_t e;
+#define HIPCHK(x)              \
+  do {                         \
+    e = (x);                   \
+    if (e != hipSuccess) {     \
+      (void)hipGetLastError(); \
+      return map_err(e);       \
+    }                          \
+  } while (0)
+
+  HIPCHK(launch_fill_outputs(d_len, d_nodes, n, st));
+  if (n == 0) return BPIDA_OK;
+  const int D = (int)O.frontier_depth;
+  const int cap = (int)O.lds_stack_capacity;
+  const int spill_cap = (int)O.spill_capacity;
+
+  // a1: ingest
+  HIPCHK(W.inst.ensure(sizeof(Inst) * (size_t)n));
+  HIPCHK(launch_ingest4(d_states, n, W.inst.as<Inst>(), st));
+  std::vector<Inst> inst((size_t)n);
+  HIPCHK(hipMemcpyAsync(inst.data(), W.inst.p, sizeof(Inst) * (size_t)n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+
+  // a3: split-tree layout (exact level sizes per instance)
+  const int L1 = kMaxDepth + 1;
+  std::vector<int32_t> lc((size_t)n * L1, 0);
+  std::vector<int64_t> off((size_t)n + 1, 0);
+  std::vector<int64_t> root_off((size_t)n, 0);
+  for (int i = 0; i < n; ++i) {
+    int32_t* row = lc.data() + (size_t)i * L1;
+    if (inst[i].status == 0) level_sizes(inst[i].blank, D, row);
+    else row[0] = 1;
+    int64_t tot = 0;
+    for (int d = 0; d <= D; ++d) {
+      if (d == D) root_off[i] = off[i] + tot;
+      tot += row[d];
+    }
+    off[i + 1] = off[i] + tot;
+  }
+  HIPCHK(W.tree.ensure(sizeof(Node) * (size_t)off[n]));
+  HIPCHK(W.tree_off.ensure(sizeof(int64_t) * (size_t)n));
+  HIPCHK(W.level_cnt.ensure(sizeof(int32_t) * lc.size()));
+  HIPCHK(W.hist.ensure(sizeof(uint32_t) * kHistBins * (size_t)n));
+  HIPCHK(W.goal_g.ensure(sizeof(int32_t) * (size_t)n));
+  HIPCHK(W.err.ensure(sizeof(int32_t)));
+  HIPCHK(hipMemcpyAsync(W.tree_off.p, off.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(W.level_cnt.p, lc.data(), sizeof(int32_t) * lc.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_zero_i32(W.err.as<int32_t>(), 1, st));
+  HIPCHK(launch_split4(W.inst.as<Inst>(), n, D, W.tree_off.as<int64_t>(), W.level_cnt.as<int32_t>(),
+                       W.tree.as<Node>(), W.hist.as<uint32_t>(), W.goal_g.as<int32_t>(),
+                       W.err.as<int32_t>(), st));
+  int32_t split_err = 0;
+  HIPCHK(hipMemcpyAsync(&split_err, W.err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (split_err) return BPIDA_EINTERNAL;
+
+  // a4..a9: persistent search grid and its scratch
+  int per_cu = search4_max_blocks_per_cu(cap);
+  if (per_cu <= 0) return BPIDA_EDEVICE;
+  int64_t max_grid = (int64_t)per_cu * W.num_cu;
+  if (O.max_workgroups > 0) max_grid = std::min<int64_t>(max_grid, O.max_workgroups);
+  HIPCHK(W.part.ensure(sizeof(Partial) * (size_t)max_grid));
+  HIPCHK(W.spill_t.ensure(sizeof(uint64_t) * (size_t)max_grid * spill_cap));
+  HIPCHK(W.spill_m.ensure(sizeof(uint16_t) * (size_t)max_grid * spill_cap));
+  HIPCHK(W.cursor.ensure(sizeof(int32_t)));
+  HIPCHK(W.res.ensure(sizeof(LimitResult)));
+  HIPCHK(launch_zero_i32(W.cursor.as<int32_t>(), 1, st));
+
+  int rc = BPIDA_OK;
+  for (int i = 0; i < n; ++i) {
+    int code = inst[i].status;
+    if (code == BPIDA_OK) {
+      const int nroots = lc[(size_t)i * L1 + D];
+      const Node* roots = W.tree.as<Node>() + root_off[i];
+      const int grid = (int)std::min<int64_t>(nroots, max_grid);
+      int L = inst[i].h0;
+      code = BPIDA_ELIMIT;
+      for (int j = 0; j < BPIDA_MAX_THRESHOLDS; ++j) {
+        if (L > kMaxLimit || (O.max_threshold >= 0 && L > O.max_threshold)) break;
+        HIPCHK(hipEventRecord(W.ev0, st));
+        HIPCHK(launch_search4(cap, grid, roots, nroots, L, W.cursor.as<int32_t>(),
+                              W.spill_t.as<uint64_t>(), W.spill_m.as<uint16_t>(), spill_cap,
+                              W.part.as<Partial>(), st));
+        HIPCHK(hipEventRecord(W.ev1, st));
+        HIPCHK(launch_reduce(W.part.as<Partial>(), grid, W.hist.as<uint32_t>() + (size_t)i * kHistBins,
+                             W.goal_g.as<int32_t>() + i, L, j, d_nodes + (size_t)i * BPIDA_MAX_THRESHOLDS,
+                             W.cursor.as<int32_t>(), W.res.as<LimitResult>(), st));
+        HIPCHK(hipMemcpyAsync(W.h_res, W.res.p, sizeof(LimitResult), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        float ms = 0.f;
+        if (grid > 0 && hipEventElapsedTime(&ms, W.ev0, W.ev1) == hipSuccess)
+          stats[4] += (uint64_t)(ms * 1000.0f);
+        const LimitResult R = *W.h_res;
+        stats[0] += R.rounds;
+        stats[1] += R.searched;
+        stats[2] += R.spilled;
+        stats[3] += grid > 0 ? 1 : 0;
+        stats[5] = std::max<uint64_t>(stats[5], (uint64_t)R.spill_hw);
+        if (R.err) {
+          code = BPIDA_ENOMEM;
+          break;
+        }
+        if (R.found) {
+          HIPCHK(launch_set_len(d_len + i, L, st));
+          code = BPIDA_OK;
+          break;
+        }
+        if (R.fnext != L + 2) {
+          code = BPIDA_EINTERNAL;
+          break;
+        }
+        L = R.fnext;
+      }
+    }
+    if (code != BPIDA_OK && rc == BPIDA_OK) rc = code;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  memcpy(g_stats, stats, sizeof stats);
+#undef HIPCHK
+  return rc;
+}
+
+int check_opts(int width) {
+  if (width < BPIDA_MIN_WIDTH || width > BPIDA_MAX_WIDTH) return BPIDA_EINVAL;
+  return BPIDA_OK;
+}
+
+}  // namespace
+}  // namespace bpida
+
+using namespace bpida;
+
+extern "C" int bpida_solve(const uint8_t* states, int32_t n_instances, int32_t width,
+                           int32_t* out_len, uint64_t* out_nodes_per_threshold) {
+  try {
+    if (!states || !out_len || !out_nodes_per_threshold || n_instances < 0) return BPIDA_EINVAL;
+    if (check_opts(width) != BPIDA_OK) return BPIDA_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    const Options O = g_opt;
+    const size_t n = (size_t)n_instances;
+    if (n == 0) return BPIDA_OK;
+    int rc = ensure_device();
+    if (rc != BPIDA_OK) return rc;
+    Workspace& W = g_ws;
+    hipStream_t st = nullptr;
+    if (W.h2d_states.ensure(n * 16) != hipSuccess || W.out_len.ensure(n * sizeof(int32_t)) != hipSuccess ||
+        W.out_nodes.ensure(n * BPIDA_MAX_THRESHOLDS * sizeof(uint64_t)) != hipSuccess)
+      return BPIDA_ENOMEM;
+    if (hipMemcpyAsync(W.h2d_states.p, states, n * 16, hipMemcpyHostToDevice, st) != hipSuccess)
+      return BPIDA_EDEVICE;
+    rc = run_plain(W.h2d_states.as<uint8_t>(), (int)n, W.out_len.as<int32_t>(),
+                   W.out_nodes.as<uint64_t>(), st, O);
+    if (hipMemcpyAsync(out_len, W.out_len.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(out_nodes_per_threshold, W.out_nodes.p, n * BPIDA_MAX_THRESHOLDS * sizeof(uint64_t),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return BPIDA_EDEVICE;
+    return rc;
+  } catch (const std::bad_alloc&) {
+    return BPIDA_ENOMEM;
+  } catch (...) {
+    return BPIDA_EINTERNAL;
+  }
+}
+
+extern "C" int bpida_solve_device(const uint8_t* d_states, int32_t n_instances, int32_t width,
+                                  int32_t* d_len, uint64_t* d_nodes, void* hip_stream) {
+  try {
+    if (!d_states || !d_len || !d_nodes || n_instances < 0) return BPIDA_EINVAL;
+    if (check_opts(width) != BPIDA_OK) return BPIDA_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    const Options O = g_opt;
+    if (n_instances == 0) return BPIDA_OK;
+    int rc = ensure_device();
+    if (rc != BPIDA_OK) return rc;
+    return run_plain(d_states, n_instances, d_len, d_nodes, (hipStream_t)hip_stream, O);
+  } catch (const std::bad_alloc&) {
+    return BPIDA_ENOMEM;
+  } catch (...) {
+    return BPIDA_EINTERNAL;
+  }
+}
+
+extern "C" int bpida_set_option(const char* key, int64_t value) {
+  if (!key) return BPIDA_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  const std::string k(key);
+  if (k == "frontier_depth") {
+    if (value < 0 || value > kMaxDepth) return BPIDA_EINVAL;
+    g_opt.frontier_depth = value;
+  } else if (k == "lds_stack_capacity") {
+    if (value != 128 && value != 256 && value != 512 && value != 1024) return BPIDA_EINVAL;
+    g_opt.lds_stack_capacity = value;
+  } else if (k == "spill_capacity") {
+    if (value < 64 || value > (1 << 24) || value % 64) return BPIDA_EINVAL;
+    g_opt.spill_capacity = value;
+  } else if (k == "max_workgroups") {
+    if (value < 0 || value > (1 << 20)) return BPIDA_EINVAL;
+    g_opt.max_workgroups = value;
+  } else if (k == "max_threshold") {
+    if (value < -1 || value > kMaxLimit) return BPIDA_EINVAL;
+    g_opt.max_threshold = value;
+  } else {
+    return BPIDA_EINVAL;
+  }
+  return BPIDA_OK;
+}
+
+extern "C" int64_t bpida_get_option(const char* key) {
+  if (!key) return INT64_MIN;
+  std::lock_guard<std::mutex> lk(g_mu);
+  const std::string k(key);
+  if (k == "frontier_depth") return g_opt.frontier_depth;
+  if (k == "lds_stack_capacity") return g_opt.lds_stack_capacity;
+  if (k == "spill_capacity") return g_opt.spill_capacity;
+  if (k == "max_workgroups") return g_opt.max_workgroups;
+  if (k == "max_threshold") return g_opt.max_threshold;
+  return INT64_MIN;
+}
+
+extern "C" int bpida_last_stats(uint64_t* out, int32_t n) {
+  if (!out || n < 0 || n > 8) return BPIDA_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int i = 0; i < n; ++i) out[i] = g_stats[i];
+  return BPIDA_OK;
+}
+
+extern "C" const char* bpida_strerror(int code) {
+  switch (code) {
+    case BPIDA_OK: return "ok";
+    case BPIDA_EINVAL: return "invalid argument or state";
+    case BPIDA_EUNSOLVABLE: return "unsolvable state (parity)";
+    case BPIDA_ELIMIT: return "f-limit cap reached";
+    case BPIDA_ENOMEM: return "out of device memory or spill area";
+    case BPIDA_EDEVICE: return "no usable gfx950 device or HIP failure";
+    case BPIDA_EINTERNAL: return "internal consistency check failed";
+    default: return "unknown status";
+  }
+}

@@ -1,0 +1,120 @@
+// bpida_internal.h -- layouts shared by the library's host driver and kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bpida {
+
+// ---------------------------------------------------------------------------
+// 15-puzzle encoding (width 4).
+//   tiles: 16 nibbles, nibble p (bits 4p..4p+3) = tile at cell p.
+//   goal:  tile p at cell p.
+//   moves: blank moves U=0 (-4), L=1 (-1), R=2 (+1), D=3 (+4); inverse 3-a.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kGoal4 = 0xFEDCBA9876543210ull;
+
+// Bit 4*b + a is set iff move a keeps a blank at cell b on the board.
+constexpr uint64_t make_move_mask4() {
+  uint64_t m = 0;
+  for (int b = 0; b < 16; ++b) {
+    const int r = b >> 2, c = b & 3;
+    if (r > 0) m |= 1ull << (4 * b + 0);
+    if (c > 0) m |= 1ull << (4 * b + 1);
+    if (c < 3) m |= 1ull << (4 * b + 2);
+    if (r < 3) m |= 1ull << (4 * b + 3);
+  }
+  return m;
+}
+constexpr uint64_t kMoveMask4 = make_move_mask4();
+
+// Manhattan delta table (Sec. 3 heuristic, applied incrementally).  Move a
+// slides the tile t standing at the blank's neighbour n into the blank's
+// cell b.  Only one coordinate of t changes: its row for U/D, its column
+// for L/R.  With ct = that coordinate of t's goal cell (= of t) and cn = that
+// coordinate of n, the tile's distance grows by one iff it moves away from
+// its goal coordinate, otherwise it shrinks by one.  Bits 16a + 4ct + cn hold
+// "grows" for move a.
+constexpr uint64_t make_dh_table4() {
+  uint64_t tab = 0;
+  for (int a = 0; a < 4; ++a)
+    for (int ct = 0; ct < 4; ++ct)
+      for (int cn = 0; cn < 4; ++cn) {
+        // coordinate after the move: U moves the tile down (+1), D up (-1),
+        // L moves it right (+1), R left (-1)
+        const int step = (a == 0 || a == 1) ? 1 : -1;
+        const int before = ct > cn ? ct - cn : cn - ct;
+        const int cafter = cn + step;
+        const int after = ct > cafter ? ct - cafter : cafter - ct;
+        if (after > before) tab |= 1ull << (16 * a + 4 * ct + cn);
+      }
+  return tab;
+}
+constexpr uint64_t kDhTable4 = make_dh_table4();
+
+// A node of the split tree, and a subtree root of the search.
+//   meta bits 0..3 blank cell, 4..6 forbidden move (inverse of the move that
+//   produced the node; 4 = none), 8..15 g, 16..23 h.
+struct alignas(16) Node {
+  uint64_t tiles;
+  uint32_t meta;
+  uint32_t f;  // g + h
+};
+
+__host__ __device__ inline uint32_t node_meta(int blank, int forbid, int g, int h) {
+  return (uint32_t)blank | ((uint32_t)forbid << 4) | ((uint32_t)g << 8) | ((uint32_t)h << 16);
+}
+
+// Ingest result per instance.
+struct Inst {
+  uint64_t tiles;
+  int32_t blank;
+  int32_t h0;
+  int32_t status;  // bpida_status
+  int32_t pad;
+};
+
+// Per-workgroup partial of one search launch.
+struct Partial {
+  uint64_t nodes;    // nodes popped (expanded)
+  uint64_t rounds;   // pop-expand-push cycles
+  uint64_t spilled;  // entries moved LDS -> HBM
+  int32_t fmin;      // smallest f of a pruned child or skipped root
+  int32_t goals;     // goal nodes expanded
+  int32_t err;       // nonzero: spill area overflow
+  int32_t spill_hw;  // high-water mark of the spill stack
+};
+
+// Per-limit result read back by the host driver.
+struct LimitResult {
+  uint64_t nodes;   // interior + searched nodes at this limit
+  int32_t fnext;    // next limit (must be limit + 2 unless found)
+  int32_t found;    // a goal was expanded
+  int32_t err;      // spill overflow in some workgroup
+  int32_t spill_hw;
+  uint64_t rounds;
+  uint64_t spilled;
+  uint64_t searched;  // nodes expanded by the search kernel alone
+};
+
+constexpr int kHistBins = 256;  // f values 0..255 of the split tree's interior
+constexpr int kMaxLimit = 255;  // slack and f fit in 8 bits
+constexpr int kMaxDepth = 16;  // deepest root split
+
+// Kernel launchers (bpida_kernels.hip).
+hipError_t launch_ingest4(const uint8_t* d_states, int n, Inst* d_inst, hipStream_t s);
+hipError_t launch_split4(const Inst* d_inst, int n, int depth, const int64_t* d_tree_off,
+                         const int32_t* d_level_cnt, Node* d_tree, uint32_t* d_hist,
+                         int32_t* d_goal_g, int32_t* d_err, hipStream_t s);
+hipError_t launch_search4(int lds_cap, int grid, const Node* d_roots, int nroots, int limit,
+                          int32_t* d_cursor, uint64_t* d_spill_tiles, uint16_t* d_spill_meta,
+                          int spill_cap, Partial* d_part, hipStream_t s);
+hipError_t launch_reduce(const Partial* d_part, int nwg, const uint32_t* d_hist_i,
+                         const int32_t* d_goal_g_i, int limit, int col, uint64_t* d_nodes_row,
+                         int32_t* d_cursor, LimitResult* d_res, hipStream_t s);
+hipError_t launch_fill_outputs(int32_t* d_len, uint64_t* d_nodes, int n, hipStream_t s);
+hipError_t launch_set_len(int32_t* d_len_i, int32_t value, hipStream_t s);
+hipError_t launch_zero_i32(int32_t* d_p, int n, hipStream_t s);
+int search4_max_blocks_per_cu(int lds_cap);
+
+}  // namespace bpida

@@ -1,0 +1,76 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry
+point, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1705_02843_amd import bpida
+    return bpida
+
+
+def declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*(bpida_[a-z_0-9]+)\s*\(",
+                                text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(B):
+    names = declared_functions()
+    assert "bpida_solve" in names and "bpida_solve_device" in names
+    for nm in names:
+        assert hasattr(B.lib, nm), nm
+    assert set(B.EXPORTS) == set(names)
+
+
+def test_argument_errors_before_device_work(B):
+    P = ctypes.POINTER
+    st = np.zeros(16, np.uint8)
+    ln = np.zeros(1, np.int32)
+    nd = np.zeros(64, np.uint64)
+    sp = st.ctypes.data_as(P(ctypes.c_uint8))
+    lp = ln.ctypes.data_as(P(ctypes.c_int32))
+    npp = nd.ctypes.data_as(P(ctypes.c_uint64))
+    assert B.lib.bpida_solve(None, 1, 4, lp, npp) == B.EINVAL
+    assert B.lib.bpida_solve(sp, 1, 4, None, npp) == B.EINVAL
+    assert B.lib.bpida_solve(sp, 1, 4, lp, None) == B.EINVAL
+    assert B.lib.bpida_solve(sp, -1, 4, lp, npp) == B.EINVAL
+    assert B.lib.bpida_solve(sp, 1, 7, lp, npp) == B.EINVAL
+    assert B.lib.bpida_solve(sp, 0, 4, lp, npp) == B.OK  # empty batch: nothing to do
+    assert B.lib.bpida_solve_device(None, 1, 4, None, None, None) == B.EINVAL
+    assert B.lib.bpida_solve_device(ctypes.c_void_p(8), 0, 4, ctypes.c_void_p(8),
+                                    ctypes.c_void_p(8), None) == B.OK
+    assert (ln == 0).all() and (nd == 0).all()  # outputs untouched
+
+
+def test_options_roundtrip_and_validation(B):
+    old = B.get_option("frontier_depth")
+    B.set_option("frontier_depth", 6)
+    assert B.get_option("frontier_depth") == 6
+    B.set_option("frontier_depth", old)
+    for k, v in (("frontier_depth", 17), ("frontier_depth", -1), ("lds_stack_capacity", 300),
+                 ("spill_capacity", 65), ("max_threshold", -2), ("no_such_key", 1)):
+        with pytest.raises(B.BpidaError):
+            B.set_option(k, v)
+    assert B.get_option("no_such_key") == -(2 ** 63)
+
+
+def test_strerror_covers_codes(B):
+    texts = {B.strerror(c) for c in (0, -1, -2, -3, -4, -5, -6)}
+    assert len(texts) == 7 and B.strerror(-99) == "unknown status"
+
+
+def test_last_stats_shape(B):
+    s = B.last_stats()
+    assert set(s) >= {"rounds", "search_nodes", "spilled", "launches", "search_us"}

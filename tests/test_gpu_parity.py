@@ -1,0 +1,200 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bit-exact on every output (integer search): optimal lengths and the node
+count of every f-limit, final limit run to completion.  Full-size cases use
+the stored oracle results in tests/golden/ (written by make_golden.py from the
+oracle alone); small cases call the oracle directly.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU test on a box without a GPU"
+    from paper_1705_02843_amd import bpida
+    return bpida
+
+
+@pytest.fixture
+def opts(B):
+    keys = ("frontier_depth", "lds_stack_capacity", "spill_capacity", "max_workgroups",
+            "max_threshold")
+    saved = {k: B.get_option(k) for k in keys}
+    yield B
+    for k, v in saved.items():
+        B.set_option(k, v)
+
+
+def load_golden(name):
+    g = json.load(open(os.path.join(GOLDEN, name + ".json")))
+    states = np.array([[int(c, 16) for c in rec["state"]] for rec in g["instances"]], np.uint8)
+    n = len(g["instances"])
+    length = np.array([rec["length"] for rec in g["instances"]], np.int32)
+    nodes = np.zeros((n, 64), np.uint64)
+    for i, rec in enumerate(g["instances"]):
+        nodes[i, :len(rec["nodes"])] = rec["nodes"]
+        h0 = rec["limits"][0]
+        assert rec["limits"] == [h0 + 2 * j for j in range(len(rec["limits"]))]
+    return states, length, nodes
+
+
+def oracle_expect(states, width=4):
+    from oracle import oracle
+    r = oracle.solve(states, width, nthreads=8)
+    return r
+
+
+def assert_parity(got_len, got_nodes, want_len, want_nodes, tag=""):
+    bad = np.nonzero((got_len != want_len) | (got_nodes != want_nodes).any(axis=1))[0]
+    assert bad.size == 0, "%s: %d instances differ, first %d: len %d vs %d, nodes %s vs %s" % (
+        tag, bad.size, bad[0], got_len[bad[0]], want_len[bad[0]],
+        got_nodes[bad[0], :12].tolist(), want_nodes[bad[0], :12].tolist())
+
+
+def test_walk40_64_instances_exact(B):
+    _say("case: c1_walk40 full, default options")
+    states, want_len, want_nodes = load_golden("c1_walk40")
+    rc, ln, nodes = B.solve_raw(states)
+    assert rc == B.OK, B.strerror(rc)
+    assert_parity(ln, nodes, want_len, want_nodes, "c1")
+
+
+def test_md30_38_100_instances_exact(B):
+    _say("case: c2_md30_38 full (100 instances, 2.2e10 nodes), default options")
+    states, want_len, want_nodes = load_golden("c2_md30_38")
+    rc, ln, nodes = B.solve_raw(states)
+    assert rc == B.OK, B.strerror(rc)
+    assert_parity(ln, nodes, want_len, want_nodes, "c2")
+    st = B.last_stats()
+    _say("c2 stats: %s" % st)
+
+
+@pytest.mark.parametrize("depth", [0, 1, 2, 5, 8, 12])
+def test_split_depths_agree(opts, depth):
+    B = opts
+    _say("case: c1 first 24, frontier_depth=%d" % depth)
+    states, want_len, want_nodes = load_golden("c1_walk40")
+    states, want_len, want_nodes = states[:24], want_len[:24], want_nodes[:24]
+    B.set_option("frontier_depth", depth)
+    rc, ln, nodes = B.solve_raw(states)
+    assert rc == B.OK, B.strerror(rc)
+    assert_parity(ln, nodes, want_len, want_nodes, "D=%d" % depth)
+
+
+@pytest.mark.parametrize("cap", [128, 256, 1024])
+def test_lds_capacity_and_spill_agree(opts, cap):
+    B = opts
+    _say("case: c2 first 6, lds_stack_capacity=%d, depth 6" % cap)
+    states, want_len, want_nodes = load_golden("c2_md30_38")
+    pick = [1, 4, 17, 26, 39, 77]
+    states, want_len, want_nodes = states[pick], want_len[pick], want_nodes[pick]
+    B.set_option("lds_stack_capacity", cap)
+    B.set_option("frontier_depth", 6)
+    rc, ln, nodes = B.solve_raw(states)
+    assert rc == B.OK, B.strerror(rc)
+    assert_parity(ln, nodes, want_len, want_nodes, "cap=%d" % cap)
+    if cap == 128:
+        assert B.last_stats()["spilled"] > 0  # the spill path was exercised
+
+
+@pytest.mark.parametrize("maxwg", [1, 7, 300])
+def test_grid_size_does_not_change_counts(opts, maxwg):
+    B = opts
+    _say("case: c1 first 16, max_workgroups=%d" % maxwg)
+    states, want_len, want_nodes = load_golden("c1_walk40")
+    states, want_len, want_nodes = states[:16], want_len[:16], want_nodes[:16]
+    B.set_option("max_workgroups", maxwg)
+    rc, ln, nodes = B.solve_raw(states)
+    assert rc == B.OK
+    assert_parity(ln, nodes, want_len, want_nodes, "maxwg=%d" % maxwg)
+
+
+def test_short_walks_goal_inside_split_tree(opts):
+    B = opts
+    from paper_1705_02843_amd import instances as I
+    _say("case: walks of 0..14 moves, depth 10 (goal inside the split tree)")
+    rng = np.random.Generator(np.random.PCG64(77))
+    states = np.stack([I.random_walk(rng, 4, k)[0] for k in range(15) for _ in range(3)])
+    want = oracle_expect(states)
+    B.set_option("frontier_depth", 10)
+    rc, ln, nodes = B.solve_raw(states)
+    assert rc == B.OK
+    assert_parity(ln, nodes, want.length, want.nodes, "short")
+
+
+def test_invalid_and_unsolvable_mixed_in(B):
+    _say("case: batch with invalid and unsolvable states")
+    states, want_len, want_nodes = load_golden("c1_walk40")
+    s = states[:5].copy()
+    s[1, 1], s[1, 2] = s[1, 2], s[1, 1]     # odd permutation: unsolvable
+    s[3, 0] = s[3, 5]                         # duplicate tile: invalid
+    rc, ln, nodes = B.solve_raw(s)
+    assert rc == B.EUNSOLVABLE  # first failure in instance order
+    assert ln[1] == -1 and ln[3] == -1 and (nodes[[1, 3]] == 0).all()
+    ok = [0, 2, 4]
+    assert_parity(ln[ok], nodes[ok], want_len[ok], want_nodes[ok], "mixed")
+
+
+def test_goal_and_one_move(B):
+    _say("case: goal state and one-move states")
+    g = np.arange(16, dtype=np.uint8)
+    r1 = g.copy(); r1[0], r1[1] = 1, 0
+    d1 = g.copy(); d1[0], d1[4] = 4, 0
+    rc, ln, nodes = B.solve_raw(np.stack([g, r1, d1]))
+    assert rc == B.OK
+    assert ln.tolist() == [0, 1, 1]
+    assert nodes[:, 0].tolist() == [1, 2, 2] and (nodes[:, 1:] == 0).all()
+
+
+def test_limit_cap_keeps_completed_counts(opts):
+    B = opts
+    _say("case: max_threshold cap")
+    states, want_len, want_nodes = load_golden("c1_walk40")
+    s = states[:4]
+    h0 = [int(want_len[i]) for i in range(4)]
+    B.set_option("max_threshold", 24)
+    rc, ln, nodes = B.solve_raw(s)
+    for i in range(4):
+        if want_len[i] <= 24:
+            assert ln[i] == want_len[i] and (nodes[i] == want_nodes[i]).all()
+        else:
+            assert ln[i] == -1 and rc == B.ELIMIT
+            k = int((nodes[i] != 0).sum())
+            assert (nodes[i, :k] == want_nodes[i, :k]).all()
+    del h0
+
+
+def test_device_entry_on_torch_stream(B):
+    import torch
+    _say("case: bpida_solve_device on a side stream")
+    states, want_len, want_nodes = load_golden("c1_walk40")
+    d_states = torch.from_numpy(states).cuda()
+    d_len = torch.full((64,), -9, dtype=torch.int32, device="cuda")
+    d_nodes = torch.full((64, 64), 7, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        rc = B.solve_device(d_states, d_len, d_nodes, stream=s)
+    s.synchronize()
+    assert rc == B.OK
+    assert_parity(d_len.cpu().numpy(), d_nodes.cpu().numpy().view(np.uint64), want_len,
+                  want_nodes, "device")
+
+
+def test_empty_batch(B):
+    rc, ln, nodes = B.solve_raw(np.zeros((0, 16), np.uint8))
+    assert rc == B.OK and ln.size == 0
