@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the gfx950 Block-Parallel IDA* path.
+
+One step = one full ``bpida_solve_device`` call over the workload's batch
+(ingest, root split, every f-limit of every instance with its search launch
+and reduction, outputs), with the start states already resident in HBM.
+
+Prints one JSON line: nodes expanded per second over the timed steps (the
+node total is the sum over instances and f-limits of the expanded-node
+counts, final limit run to completion), instances per second, the search
+kernel's position against the VALU integer-issue roofline, and the CPU
+oracle's rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "nodes expanded/sec and instances/sec (15-puzzle, Manhattan), batched vs plain"
+
+# MI355X integer VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one
+# 32-bit integer operation per lane per clock; no packed integer issue).
+PEAK_INT_GOPS = 256 * 64 * 2.4
+# Algorithmic integer operations per expanded node (derivation in the design
+# notes): per generated move 15 (applicability 2, successor 7, f 4,
+# compare 1, push-or-min 1) x 4 moves, plus 4 per node (pop, goal test,
+# count, parent bookkeeping).
+OPS_PER_NODE = 64
+
+WORKLOADS = {
+    "c2_md30_38": ("100 15-puzzle states from seeded 300-move non-backtracking walks, Manhattan "
+                   "30..38; plain BPIDA*: one instance per launch sequence", 4),
+    "c1_walk40": ("64 15-puzzle states from seeded 40-move non-backtracking walks; plain BPIDA*", 4),
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1705_02843_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, fn), "rb") as f:
+            h.update(fn.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def make_states(name):
+    from paper_1705_02843_amd import instances
+    return getattr(instances, name)()[0]
+
+
+def golden_total(name):
+    path = os.path.join(ROOT, "tests", "golden", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return int(json.load(f)["total_nodes"])
+
+
+def cpu_baseline(name, states, budget_nodes, nthreads):
+    """The oracle, untouched, on a bounded sample: instances taken in order,
+    skipping any whose stored node total alone exceeds a thread's share, until
+    the sample holds about ``budget_nodes`` nodes."""
+    from oracle import oracle
+    path = os.path.join(ROOT, "tests", "golden", name + ".json")
+    with open(path) as f:
+        per = [sum(r["nodes"]) for r in json.load(f)["instances"]]
+    share = budget_nodes / max(1, nthreads) * 2
+    pick, tot = [], 0
+    for i, n in enumerate(per):
+        if n > share:
+            continue
+        pick.append(i)
+        tot += n
+        if tot >= budget_nodes:
+            break
+    t0 = time.perf_counter()
+    r = oracle.solve(states[pick], 4, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    assert r.rc == 0
+    return {"value": round(r.total_nodes / dt, 1), "unit": "nodes/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": "%d of the workload's instances (%d nodes, %.1f s wall, %d threads)" % (
+                len(pick), r.total_nodes, dt, nthreads)}
+
+
+def load_traffic(src_hash):
+    """Per-launch HBM bytes of the search kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "search4_c2_md30_38_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != src_hash:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2_md30_38", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-budget-nodes", type=float, default=4e9)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run one device copy of this size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(instances shard across GPUs with no exchange; see the design notes)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1705_02843_amd import bpida
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    desc, width = WORKLOADS[args.workload]
+    states = make_states(args.workload)
+    n = states.shape[0]
+    d_states = torch.from_numpy(states).cuda()
+    d_len = torch.empty(n, dtype=torch.int32, device="cuda")
+    d_nodes = torch.empty((n, bpida.MAX_THRESHOLDS), dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    if args.calibrate_copy_mib:
+        nb = args.calibrate_copy_mib << 20
+        x = torch.empty(nb, dtype=torch.uint8, device="cuda").fill_(1)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
+    def step():
+        rc = bpida.solve_device(d_states, d_len, d_nodes, width=width, stream=stream)
+        if rc != bpida.OK:
+            raise bpida.BpidaError(rc, "bpida_solve_device")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    expect = golden_total(args.workload)
+    nodes_per_step = None
+    search_nodes = search_us = launches = rounds = spilled = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        st = bpida.last_stats()
+        search_nodes += st["search_nodes"]
+        search_us += st["search_us"]
+        launches += st["launches"]
+        rounds += st["rounds"]
+        spilled += st["spilled"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    nodes_per_step = int(d_nodes.cpu().numpy().view(np.uint64).sum(dtype=np.uint64))
+    lens = d_len.cpu().numpy()
+    if expect is not None and nodes_per_step != expect:
+        raise SystemExit("node total %d differs from the stored oracle total %d" % (nodes_per_step,
+                                                                                    expect))
+    assert (lens >= 0).all()
+    total_nodes = nodes_per_step * args.steps
+    value = total_nodes / dt
+    avg_launch_s = (search_us / launches) * 1e-6 if launches else float("nan")
+    ops_per_launch = search_nodes * OPS_PER_NODE / launches if launches else 0.0
+    achieved = ops_per_launch / avg_launch_s / 1e9 if launches else 0.0
+    src_hash = kernel_source_hash()
+    traffic = load_traffic(src_hash)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "nodes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "n_instances": n,
+                   "mode": "plain",
+                   "frontier_depth": bpida.get_option("frontier_depth"),
+                   "lds_stack_capacity": bpida.get_option("lds_stack_capacity")},
+        "instances_per_s": round(n * args.steps / dt, 2),
+        "nodes_per_step": nodes_per_step,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 1), "peak": round(PEAK_INT_GOPS, 1),
+                     "unit": "Gop/s", "frac": round(achieved / PEAK_INT_GOPS, 4),
+                     "traffic": traffic,
+                     "kernel": "search4_kernel<%d>" % bpida.get_option("lds_stack_capacity"),
+                     "ops_per_node": OPS_PER_NODE,
+                     "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                     "launches_per_step": launches // max(1, args.steps),
+                     "search_nodes_per_s_in_kernel": round(search_nodes / (search_us * 1e-6), 1)
+                     if search_us else None},
+        "search_rounds_per_step": rounds // max(1, args.steps),
+        "pop_occupancy": round(search_nodes / (16.0 * rounds), 4) if rounds else None,
+        "spilled_per_step": spilled // max(1, args.steps),
+        "kernel_source_hash": src_hash,
+    }
+    if not args.no_cpu_baseline:
+        nthreads = min(16, os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline(args.workload, states, args.cpu_budget_nodes, nthreads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
