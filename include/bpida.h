@@ -89,11 +89,28 @@ int bpida_solve_device(const uint8_t *d_states, int32_t n_instances, int32_t wid
 
 /*
  * Set a tuning or control option for subsequent calls (process-wide).
- *   "frontier_depth"     depth D of the root split, 0..16 (default 10)
+ *   "mode"               1 = batched (default): one persistent launch searches
+ *                        all instances through all limits from a device work
+ *                        queue with work donation between workgroups and
+ *                        the limit advanced on the device; 0 = plain: Alg. 1
+ *                        as printed, one search launch per instance and limit,
+ *                        one subtree root per workgroup, no balancing
+ *   "frontier_depth"     depth D of the root split, 0..16, or -1 (default):
+ *                        10 in plain mode, 6 in batched mode
  *   "lds_stack_capacity" DFS stack entries per workgroup in LDS: 128, 256,
  *                        512 or 1024 (default 512); deeper entries spill
- *   "spill_capacity"     per-workgroup HBM spill entries, a multiple of 64
- *                        (default 16384)
+ *   "spill_capacity"     plain mode: per-workgroup HBM spill entries, a
+ *                        multiple of 64 (default 16384)
+ *   "queue_capacity"     batched mode: queue slots of 64 entries (rounded up
+ *                        to a power of two, at least 64; 0 = sized from the
+ *                        batch); a queue that stays full while a workgroup
+ *                        pushes makes the call return BPIDA_ENOMEM
+ *   "watchdog_ms"        batched mode: a workgroup that finds no work for
+ *                        this long while instances remain stops and the call
+ *                        returns BPIDA_EINTERNAL (default 20000)
+ *   "budget_ms"          batched mode: every workgroup of the persistent launch
+ *                        stops after this long and the call returns
+ *                        BPIDA_EINTERNAL (default 600000)
  *   "max_workgroups"     cap on the persistent search grid (0 = occupancy)
  *   "max_threshold"      stop with BPIDA_ELIMIT before a limit above this
  *                        (-1 = none, default)
@@ -109,11 +126,18 @@ int64_t bpida_get_option(const char *key);
  *   out[0] search rounds (pop-expand-push cycles, the repetitions of BPDFS's
  *          loop), summed over workgroups and limits
  *   out[1] nodes expanded by the search kernel (interior split nodes excluded)
- *   out[2] entries spilled from LDS to HBM
+ *   out[2] entries moved from LDS to HBM (plain: spills; batched: donated
+ *          or spilled chunks x 64)
  *   out[3] search-kernel launches
  *   out[4] search-kernel time in microseconds (device events, summed)
- *   out[5] largest per-workgroup spill stack seen, in entries
- * n = number of slots to fill (<= 8).  Returns BPIDA_OK or BPIDA_EINVAL.
+ *   out[5] plain mode: largest per-workgroup spill stack seen, in entries
+ *   out[6] batched mode: chunks pushed to the work queue (seeds excluded)
+ *   out[7] batched mode: chunks popped from the work queue
+ *   out[8..10] batched mode: microseconds summed over workgroups spent
+ *          searching, taking work from the queue, and idle
+ *   out[11] batched mode: donations made because workgroups were idle
+ *   out[12] batched mode: workgroups in the persistent grid
+ * n = number of slots to fill (<= 16).  Returns BPIDA_OK or BPIDA_EINVAL.
  */
 int bpida_last_stats(uint64_t *out, int32_t n);
 

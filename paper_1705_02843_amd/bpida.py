@@ -68,11 +68,13 @@ def get_option(key: str) -> int:
 
 
 def last_stats() -> dict:
-    out = (ctypes.c_uint64 * 8)()
-    rc = lib.bpida_last_stats(out, 8)
+    out = (ctypes.c_uint64 * 16)()
+    rc = lib.bpida_last_stats(out, 16)
     if rc != OK:
         raise BpidaError(rc, "last_stats")
-    keys = ("rounds", "search_nodes", "spilled", "launches", "search_us", "spill_high_water")
+    keys = ("rounds", "search_nodes", "spilled", "launches", "search_us", "spill_high_water",
+            "chunks_pushed", "chunks_popped", "wg_us_search", "wg_us_queue", "wg_us_idle",
+            "donations_voluntary", "grid")
     return {k: int(out[i]) for i, k in enumerate(keys)}
 
 

@@ -1,0 +1,504 @@
+// bpida_batch.hip -- batched, persistent Block-Parallel IDA* for gfx950.
+//
+// One launch searches every instance of a batch through all of its f-limits.
+// Work lives in a device queue of chunks (up to 64 stack entries of one
+// instance at one limit).  A workgroup (one wave64) pops a chunk into its LDS
+// stack and runs BPDFS rounds (Alg. 1) on it; it gives the 64 oldest entries
+// of its stack back to the queue when its stack would overflow LDS, or when
+// other workgroups are idle and the queue holds fewer chunks than there are
+// workgroups waiting for work (donation; the paper's BPIDA* balances statically, its
+// intra-block donation idea for PFullLB is applied here across workgroups).
+//
+// Per instance, `outstanding` counts its chunks that are queued or held by a
+// workgroup at the current limit.  The workgroup whose decrement brings it to
+// zero completes the limit on the device: it adds the split tree's interior
+// nodes, writes the node count of the limit, stops on a goal (all optimal
+// solutions: the limit has been searched to completion), and otherwise
+// advances the limit by 2 and seeds the instance's subtree roots again.
+#include <limits.h>
+
+#include "bpida_internal.h"
+#include "bpida_round.h"
+
+namespace bpida {
+
+#define AGENT __HIP_MEMORY_SCOPE_AGENT
+
+__device__ __forceinline__ uint64_t ld_relaxed(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, AGENT);
+}
+__device__ __forceinline__ int32_t ld_relaxed(int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// Ticket queue of chunks.  Producers and consumers take tickets with a
+// fetch-and-add on tail / head (no compare-and-swap loops, which collapse
+// under thousands of contending workgroups).  Slot k of the ring carries a
+// sequence number: seq == t means "free for producer ticket t", seq == t + 1
+// means "holds the chunk of ticket t".  An idle workgroup takes one consumer
+// ticket and then polls only its own slot, so waiting workgroups do not
+// contend on a shared line; head - tail = waiting workgroups - queued chunks,
+// which is what a busy workgroup reads to decide whether to donate.  Every
+// operation is done by a whole wave: lane 0 handles tickets, all lanes move
+// the 64 entries.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kNoTicket = ~0ull;
+constexpr int kPushSpin = 1 << 16;  // bounded wait for a slot still being read
+
+__device__ __forceinline__ uint64_t bcast64(uint64_t v) {
+  const uint32_t lo = (uint32_t)wave_bcast((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)wave_bcast((int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Returns false only if the ring stayed full for the whole bounded wait.
+__device__ bool q_push(const BatchArgs& A, uint64_t tile, uint16_t meta, int count, int inst) {
+  const int lane = threadIdx.x;
+  QueueCtl* q = A.q;
+  const uint64_t mask = A.qmask;
+  uint64_t pos = 0;
+  int ok = 0;
+  if (lane == 0) {
+    pos = __hip_atomic_fetch_add(&q->tail, (uint64_t)1, __ATOMIC_RELAXED, AGENT);
+    for (int k = 0; k < kPushSpin; ++k) {
+      if (ld_relaxed(&A.seq[pos & mask]) == pos) {
+        ok = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  ok = wave_bcast(ok);
+  if (!ok) {
+    if (lane == 0) atomicOr(&q->err, 16);  // ticket lost: the call reports BPIDA_ENOMEM
+    return false;
+  }
+  pos = bcast64(pos);
+  // the slot's previous consumer released it; order the new payload after
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  QChunk* c = A.slots + (pos & mask);
+  c->tiles[lane] = tile;
+  c->meta[lane] = meta;
+  if (lane == 0) {
+    c->inst = inst;
+    c->count = count;
+  }
+  __syncthreads();  // one-wave workgroup: every lane's stores precede lane 0's release
+  if (lane == 0) __hip_atomic_store(&A.seq[pos & mask], pos + 1, __ATOMIC_RELEASE, AGENT);
+  return true;
+}
+
+// Takes a consumer ticket if `ticket` holds none, then checks whether that
+// ticket's chunk has arrived.  Returns true with the chunk, or false (the
+// ticket is kept for the next call).
+__device__ bool q_take(const BatchArgs& A, uint64_t& ticket, uint64_t& tile, uint16_t& meta,
+                       int& count, int& inst) {
+  const int lane = threadIdx.x;
+  QueueCtl* q = A.q;
+  const uint64_t mask = A.qmask;
+  int ready = 0;
+  if (lane == 0) {
+    if (ticket == kNoTicket) ticket = __hip_atomic_fetch_add(&q->head, (uint64_t)1, __ATOMIC_RELAXED, AGENT);
+    ready = ld_relaxed(&A.seq[ticket & mask]) == ticket + 1;
+  }
+  ticket = bcast64(ticket);
+  if (!wave_bcast(ready)) return false;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const QChunk* c = A.slots + (ticket & mask);
+  tile = c->tiles[lane];
+  meta = c->meta[lane];
+  count = wave_bcast(c->count);
+  inst = wave_bcast(c->inst);
+  __syncthreads();  // all lanes have read the slot before it is handed back
+  if (lane == 0) __hip_atomic_store(&A.seq[ticket & mask], ticket + mask + 1, __ATOMIC_RELEASE, AGENT);
+  ticket = kNoTicket;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Limit bookkeeping, executed by one wave.
+// ---------------------------------------------------------------------------
+
+// Pushes the roots of instance i with f <= limit as chunks, under a guard
+// unit so that the limit cannot complete while seeding.  Returns true if the
+// guard's release brought the instance's outstanding count to zero, i.e. the
+// caller must complete the limit itself.
+__device__ bool seed_limit(const BatchArgs& A, int i) {
+  const int lane = threadIdx.x;
+  InstState* S = A.is + i;
+  const int L = S->limit;
+  if (lane == 0) __hip_atomic_store(&S->outstanding, 1, __ATOMIC_RELAXED, AGENT);
+  const Node* roots = A.tree + S->root_off;
+  const int nroots = S->nroots;
+  int fm = INT_MAX;
+  bool full = false;
+  for (int base = 0; base < nroots && !full; base += 64) {
+    const int r = base + lane;
+    Node R;
+    R.tiles = 0;
+    R.meta = 0;
+    R.f = 0;
+    bool keep = false;
+    if (r < nroots) {
+      R = roots[r];
+      keep = (int)R.f <= L;
+      if (!keep) fm = min(fm, (int)R.f);
+    }
+    const uint64_t km = __ballot(keep);
+    const int cnt = __popcll(km);
+    if (cnt == 0) continue;
+    // compact the kept roots into lanes 0..cnt-1 through LDS
+    __shared__ uint64_t s_t[64];
+    __shared__ uint16_t s_m[64];
+    const int off = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+    if (keep) {
+      s_t[off] = R.tiles;
+      s_m[off] = stack_meta((int)(R.meta & 15u), (int)((R.meta >> 4) & 7u), L - (int)R.f);
+    }
+    WAVE_SYNC();
+    const uint64_t t = s_t[lane];
+    const uint16_t m = s_m[lane];
+    WAVE_SYNC();
+    if (lane == 0) __hip_atomic_fetch_add(&S->outstanding, 1, __ATOMIC_RELAXED, AGENT);
+    if (!q_push(A, t, m, cnt, i)) {
+      full = true;  // the remaining roots are dropped; the call reports BPIDA_ENOMEM
+      if (lane == 0) {
+        __hip_atomic_fetch_add(&S->outstanding, -1, __ATOMIC_RELAXED, AGENT);
+        atomicOr(&A.q->err, 1);
+      }
+    }
+  }
+  fm = wave_min(fm);
+  int last = 0;
+  if (lane == 0) {
+    if (fm != INT_MAX) __hip_atomic_fetch_min(&S->fmin, fm, __ATOMIC_RELAXED, AGENT);
+    last = __hip_atomic_fetch_add(&S->outstanding, -1, __ATOMIC_ACQ_REL, AGENT) == 1;
+  }
+  return wave_bcast(last) != 0;
+}
+
+// Completes the current limit of instance i (its outstanding count is zero
+// and this wave observed it), then advances it.  Loops while a new limit
+// has no queued work.
+__device__ void complete_limit(const BatchArgs& A, int i) {
+  const int lane = threadIdx.x;
+  InstState* S = A.is + i;
+  for (;;) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int L = S->limit;
+    const int col = S->col;
+    // interior nodes of the split tree (depth < D) expanded at this limit
+    const uint32_t* h = A.hist + (size_t)i * kHistBins;
+    uint64_t interior = 0;
+    int fm = INT_MAX;
+    for (int f = lane; f < kHistBins; f += 64) {
+      const uint32_t c = h[f];
+      if (f <= L) interior += c;
+      else if (c) fm = min(fm, f);
+    }
+    for (int o = 32; o > 0; o >>= 1) interior += __shfl_xor(interior, o, 64);
+    fm = wave_min(fm);
+    int state = 0;  // 0: advance, 1: solved, <0: error code
+    if (lane == 0) {
+      const uint64_t total = ld_relaxed(&S->nodes) + interior;
+      A.out_nodes[(size_t)i * 64 + col] = total;
+      const int goals = ld_relaxed(&S->goals);
+      const int fnext = min(fm, ld_relaxed(&S->fmin));
+      if (goals > 0 || A.goal_g[i] <= L) {
+        A.out_len[i] = L;
+        state = 1;
+      } else if (fnext != L + 2) {
+        state = -6;  // BPIDA_EINTERNAL
+      } else if (col + 1 >= 64 || L + 2 > A.max_limit) {
+        state = -3;  // BPIDA_ELIMIT
+      }
+      if (state != 0) {
+        __hip_atomic_store(&S->done, state, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_fetch_add(&A.q->remaining, -1, __ATOMIC_RELEASE, AGENT);
+      } else {
+        S->limit = L + 2;
+        S->col = col + 1;
+        __hip_atomic_store(&S->nodes, (uint64_t)0, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&S->fmin, INT_MAX, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&S->goals, 0, __ATOMIC_RELAXED, AGENT);
+      }
+    }
+    state = wave_bcast(state);
+    if (state != 0) return;
+    __syncthreads();
+    if (!seed_limit(A, i)) return;
+  }
+}
+
+// Adds this workgroup's counts for the unit of instance i it held and
+// releases the unit; completes the limit if it was the last unit.
+__device__ void release_unit(const BatchArgs& A, int i, uint64_t expanded, int goals, int fmin) {
+  const int lane = threadIdx.x;
+  InstState* S = A.is + i;
+  fmin = wave_min(fmin);
+  int last = 0;
+  if (lane == 0) {
+    if (expanded) __hip_atomic_fetch_add(&S->nodes, expanded, __ATOMIC_RELAXED, AGENT);
+    if (goals) __hip_atomic_fetch_add(&S->goals, goals, __ATOMIC_RELAXED, AGENT);
+    if (fmin != INT_MAX) __hip_atomic_fetch_min(&S->fmin, fmin, __ATOMIC_RELAXED, AGENT);
+    last = __hip_atomic_fetch_add(&S->outstanding, -1, __ATOMIC_ACQ_REL, AGENT) == 1;
+  }
+  if (wave_bcast(last)) complete_limit(A, i);
+}
+
+// ---------------------------------------------------------------------------
+// The persistent kernel.
+// ---------------------------------------------------------------------------
+template <int CAP>
+__global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
+  static_assert((CAP & (CAP - 1)) == 0 && CAP >= 128, "ring size");
+  __shared__ uint64_t st[CAP];
+  __shared__ uint16_t sm[CAP];
+  const int lane = threadIdx.x;
+  const LaneMap M = make_lane_map(lane);
+  QueueCtl* q = A.q;
+
+  // seed the first limit of this workgroup's share of the instances
+  for (int i = blockIdx.x; i < A.n; i += gridDim.x) {
+    if (A.is[i].done != 0) continue;
+    if (seed_limit(A, i)) complete_limit(A, i);
+  }
+
+  uint64_t rounds = 0, searched = 0, pushes = 0, pops = 0, voluntary = 0;
+  uint64_t t_work = 0, t_queue = 0, t_idle = 0;
+  uint64_t t_mark = wall_clock64();
+  int inst = -1, limit = 0;
+  uint64_t expanded = 0;
+  int goals = 0, fmin = INT_MAX;
+  int top = 0, bot = 0;
+  bool idle = false;
+  uint64_t idle_since = 0, idle_act = 0;
+  uint32_t tick = 0;
+  int backoff = 1;
+  uint64_t ticket = kNoTicket;  // consumer ticket held while idle
+  const uint64_t deadline = wall_clock64() + A.budget_ticks;
+
+  for (;;) {
+    if (top == bot) {
+      {
+        const uint64_t now = wall_clock64();
+        t_work += now - t_mark;
+        t_mark = now;
+      }
+      if (inst >= 0) {
+        release_unit(A, inst, expanded, goals, fmin);
+        searched += expanded;
+        inst = -1;
+      }
+      uint64_t t;
+      uint16_t m;
+      int cnt, ci;
+      if (!q_take(A, ticket, t, m, cnt, ci)) {
+        if (ld_relaxed(&q->remaining) <= 0) break;
+        const uint64_t now = wall_clock64();
+        // queue activity seen by this idle workgroup (lane 0's view)
+        uint64_t act = 0;
+        if (lane == 0) act = ld_relaxed(&q->head) + ld_relaxed(&q->tail);
+        act = (uint64_t)(uint32_t)wave_bcast((int)(uint32_t)act);
+        if (!idle) {
+          idle = true;
+          idle_since = now;
+          idle_act = act;
+          backoff = 1;
+        } else if (act != idle_act) {
+          idle_since = now;  // the queue moved: work is being shared
+          idle_act = act;
+        } else if (now - idle_since > A.idle_ticks || now > deadline) {
+          // no queue activity for the whole watchdog period although
+          // instances remain, or the run's time budget is spent
+          if (lane == 0) atomicOr(&q->err, now > deadline ? 8 : 4);
+          break;
+        }
+        // exponential backoff (64 .. 1024 x 64 clocks) keeps idle
+        // workgroups from flooding the queue's cache lines
+        for (int k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(64);
+        backoff = min(backoff * 2, 8);
+        {
+          const uint64_t now2 = wall_clock64();
+          t_idle += now2 - t_mark;
+          t_mark = now2;
+        }
+        continue;
+      }
+      if (idle) {
+        idle = false;
+        backoff = 1;
+      }
+      pops += 1;
+      {
+        const uint64_t now = wall_clock64();
+        t_queue += now - t_mark;
+        t_mark = now;
+      }
+      inst = ci;
+      limit = A.is[inst].limit;
+      expanded = 0;
+      goals = 0;
+      fmin = INT_MAX;
+      top = cnt;
+      bot = 0;
+      if (lane < cnt) {
+        st[lane] = t;
+        sm[lane] = m;
+      }
+      WAVE_SYNC();
+    }
+    int avail = top - bot;
+    ++tick;
+    if ((tick & 1023u) == 0 && wall_clock64() > deadline) {
+      if (lane == 0) atomicOr(&q->err, 8);
+      break;  // abandon: the call reports BPIDA_EINTERNAL
+    }
+    if (avail + 32 > CAP) {
+      // LDS would overflow: move the 64 oldest entries to the queue
+      const int p = (bot + lane) & (CAP - 1);
+      const uint64_t t = st[p];
+      const uint16_t m = sm[p];
+      WAVE_SYNC();
+      if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
+      if (q_push(A, t, m, 64, inst)) {
+        pushes += 1;
+      } else {
+        if (lane == 0) {
+          __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
+          atomicOr(&q->err, 2);  // entries dropped: the call reports BPIDA_ENOMEM
+        }
+      }
+      bot += 64;
+      avail -= 64;
+    } else if (avail >= 32 && (tick & 31u) == 0) {
+      // donation to idle workgroups when the queue holds fewer chunks than
+      // there are idle workgroups.  The oldest min(128, avail) entries (the
+      // shallowest, largest subtrees) are split alternately: donor and
+      // receiver each keep about half of that work.
+      int want = 0;
+      if (lane == 0) {
+        // consumers waiting on tickets that no queued chunk covers yet
+        const int64_t waiting = (int64_t)(ld_relaxed(&q->head) - ld_relaxed(&q->tail));
+        want = waiting > 0;
+      }
+      if (wave_bcast(want)) {
+        const int w = min(avail, 128) & ~1;
+        const int h = w >> 1;
+        const int pg = (bot + 2 * lane) & (CAP - 1);
+        const int pk = (bot + 2 * lane + 1) & (CAP - 1);
+        const uint64_t tg = st[pg], tk = st[pk];
+        const uint16_t mg = sm[pg], mk = sm[pk];
+        WAVE_SYNC();
+        if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
+        if (q_push(A, tg, mg, h, inst)) {
+          pushes += 1;
+          voluntary += 1;
+          if (lane < h) {
+            const int pn = (bot + h + lane) & (CAP - 1);
+            st[pn] = tk;
+            sm[pn] = mk;
+          }
+          WAVE_SYNC();
+          bot += h;
+          avail -= h;
+        } else if (lane == 0) {
+          __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
+        }
+      }
+    }
+    const int kp = min(avail, 16);
+    top = bp_round<CAP>(st, sm, top, kp, limit, M, goals, fmin);
+    expanded += (uint64_t)kp;
+    rounds += 1;
+  }
+  if (lane == 0) {
+    atomicAdd((unsigned long long*)&q->rounds, (unsigned long long)rounds);
+    atomicAdd((unsigned long long*)&q->searched, (unsigned long long)searched);
+    atomicAdd((unsigned long long*)&q->pushes, (unsigned long long)pushes);
+    atomicAdd((unsigned long long*)&q->pops, (unsigned long long)pops);
+    atomicAdd((unsigned long long*)&q->t_work, (unsigned long long)t_work);
+    atomicAdd((unsigned long long*)&q->t_queue, (unsigned long long)t_queue);
+    atomicAdd((unsigned long long*)&q->t_idle, (unsigned long long)t_idle);
+    atomicAdd((unsigned long long*)&q->voluntary, (unsigned long long)voluntary);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up: per-instance state, queue sequence numbers and counters.
+// ---------------------------------------------------------------------------
+__global__ void batch_setup_kernel(BatchArgs A, const Inst* __restrict__ inst,
+                                   const int64_t* __restrict__ root_off,
+                                   const int32_t* __restrict__ nroots) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k <= (int64_t)A.qmask) A.seq[k] = (uint64_t)k;
+  if (k < A.n) {
+    InstState S;
+    S.limit = inst[k].h0;
+    S.col = 0;
+    S.done = inst[k].status;  // 0 = to search
+    S.outstanding = 0;
+    S.nodes = 0;
+    S.fmin = INT_MAX;
+    S.goals = 0;
+    S.root_off = root_off[k];
+    S.nroots = nroots[k];
+    S.pad = 0;
+    if (S.done == 0 && S.limit > A.max_limit) S.done = -3;  // BPIDA_ELIMIT
+    A.is[k] = S;
+    if (S.done == 0) atomicAdd(&A.q->remaining, 1);
+  }
+}
+
+__global__ void batch_status_kernel(const InstState* __restrict__ is, int n, int32_t* __restrict__ st) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) st[k] = is[k].done;
+}
+
+hipError_t launch_batch_setup(const BatchArgs& A, const Inst* d_inst, const int64_t* d_root_off,
+                              const int32_t* d_nroots, hipStream_t s) {
+  const int64_t work = std::max<int64_t>((int64_t)A.qmask + 1, A.n);
+  hipLaunchKernelGGL(batch_setup_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, A,
+                     d_inst, d_root_off, d_nroots);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_status(const InstState* d_is, int n, int32_t* d_status, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_status_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d_is, n, d_status);
+  return hipGetLastError();
+}
+
+template <int CAP>
+static hipError_t launch_batch_t(int grid, const BatchArgs& A, hipStream_t s) {
+  hipLaunchKernelGGL(batch4_kernel<CAP>, dim3(grid), dim3(64), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch4(int lds_cap, int grid, const BatchArgs& A, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  switch (lds_cap) {
+    case 128: return launch_batch_t<128>(grid, A, s);
+    case 256: return launch_batch_t<256>(grid, A, s);
+    case 512: return launch_batch_t<512>(grid, A, s);
+    case 1024: return launch_batch_t<1024>(grid, A, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int batch4_max_blocks_per_cu(int lds_cap) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (lds_cap) {
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch4_kernel<128>, 64, 0); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch4_kernel<256>, 64, 0); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch4_kernel<512>, 64, 0); break;
+    case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch4_kernel<1024>, 64, 0); break;
+    default: break;
+  }
+  return e == hipSuccess ? nb : 0;
+}
+
+}  // namespace bpida

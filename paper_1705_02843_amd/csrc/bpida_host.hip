@@ -21,8 +21,14 @@
 namespace bpida {
 namespace {
 
+enum { kModePlain = 0, kModeBatched = 1 };
+
 struct Options {
-  int64_t frontier_depth = 10;
+  int64_t mode = kModeBatched;
+  int64_t frontier_depth = -1;  // -1: 10 for plain, 6 for batched
+  int64_t queue_capacity = 0;   // chunks; 0: sized from the batch
+  int64_t watchdog_ms = 20000;  // idle workgroups give up after this long
+  int64_t budget_ms = 600000;   // the persistent launch stops after this long
   int64_t lds_stack_capacity = 512;
   int64_t spill_capacity = 16384;
   int64_t max_workgroups = 0;
@@ -31,7 +37,7 @@ struct Options {
 
 std::mutex g_mu;  // serialises solves and option changes
 Options g_opt;
-uint64_t g_stats[8] = {0};
+uint64_t g_stats[16] = {0};
 
 // Grow-only device buffer.
 struct DevBuf {
@@ -64,8 +70,10 @@ struct DevBuf {
 struct Workspace {
   int device = -1;
   int num_cu = 0;
+  int wall_khz = 100000;
   bool arch_ok = false;
   DevBuf inst, tree, tree_off, level_cnt, hist, goal_g, err, cursor, part, spill_t, spill_m, res;
+  DevBuf qctl, qseq, qslots, istate, root_off, nroots, status;
   DevBuf h2d_states, out_len, out_nodes;
   LimitResult* h_res = nullptr;  // pinned
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -94,6 +102,9 @@ int ensure_device() {
   }
   g_ws.device = dev;
   g_ws.num_cu = prop.multiProcessorCount;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+    g_ws.wall_khz = khz;
   g_ws.arch_ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
   if (!g_ws.arch_ok) return BPIDA_EDEVICE;
   if (hipHostMalloc((void**)&g_ws.h_res, sizeof(LimitResult), hipHostMallocDefault) != hipSuccess)
@@ -126,12 +137,22 @@ void level_sizes(int blank, int depth, int32_t* out) {
   }
 }
 
-// The plain BPIDA* driver.  All buffers are device buffers; outputs are
-// written on `st`.
+int depth_for(const Options& O) {
+  if (O.frontier_depth >= 0) return (int)O.frontier_depth;
+  return O.mode == kModePlain ? 10 : 6;
+}
+
+int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes, hipStream_t st,
+                const Options& O);
+
+// The plain BPIDA* driver (Alg. 1 as printed: one search launch per f-limit
+// and instance, one root per workgroup, no dynamic balancing).  All buffers
+// are device buffers; outputs are written on `st`.
 int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes, hipStream_t st,
               const Options& O) {
+  if (O.mode == kModeBatched) return run_batched(d_states, n, d_len, d_nodes, st, O);
   Workspace& W = g_ws;
-  uint64_t stats[8] = {0};
+  uint64_t stats[16] = {0};
   hipError_t e;
 #define HIPCHK(x)              \
   do {                         \
@@ -144,7 +165,7 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
 
   HIPCHK(launch_fill_outputs(d_len, d_nodes, n, st));
   if (n == 0) return BPIDA_OK;
-  const int D = (int)O.frontier_depth;
+  const int D = depth_for(O);
   const int cap = (int)O.lds_stack_capacity;
   const int spill_cap = (int)O.spill_capacity;
 
@@ -254,6 +275,137 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
   return rc;
 }
 
+// The batched driver: one persistent launch searches every instance through
+// all of its limits (device work queue, donation, device-side limit advance).
+int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes, hipStream_t st,
+                const Options& O) {
+  Workspace& W = g_ws;
+  uint64_t stats[16] = {0};
+  hipError_t e;
+#define HIPCHK(x)              \
+  do {                         \
+    e = (x);                   \
+    if (e != hipSuccess) {     \
+      (void)hipGetLastError(); \
+      return map_err(e);       \
+    }                          \
+  } while (0)
+
+  HIPCHK(launch_fill_outputs(d_len, d_nodes, n, st));
+  if (n == 0) return BPIDA_OK;
+  const int D = depth_for(O);
+  const int cap = (int)O.lds_stack_capacity;
+
+  HIPCHK(W.inst.ensure(sizeof(Inst) * (size_t)n));
+  HIPCHK(launch_ingest4(d_states, n, W.inst.as<Inst>(), st));
+  std::vector<Inst> inst((size_t)n);
+  HIPCHK(hipMemcpyAsync(inst.data(), W.inst.p, sizeof(Inst) * (size_t)n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+
+  const int L1 = kMaxDepth + 1;
+  std::vector<int32_t> lc((size_t)n * L1, 0), nroots((size_t)n, 0);
+  std::vector<int64_t> off((size_t)n + 1, 0), root_off((size_t)n, 0);
+  int64_t seed_chunks = 0;
+  for (int i = 0; i < n; ++i) {
+    int32_t* row = lc.data() + (size_t)i * L1;
+    if (inst[i].status == 0) level_sizes(inst[i].blank, D, row);
+    else row[0] = 1;
+    int64_t tot = 0;
+    for (int d = 0; d <= D; ++d) {
+      if (d == D) root_off[i] = off[i] + tot;
+      tot += row[d];
+    }
+    off[i + 1] = off[i] + tot;
+    nroots[i] = inst[i].status == 0 ? row[D] : 0;
+    seed_chunks += (nroots[i] + kQChunk - 1) / kQChunk;
+  }
+  HIPCHK(W.tree.ensure(sizeof(Node) * (size_t)off[n]));
+  HIPCHK(W.tree_off.ensure(sizeof(int64_t) * (size_t)n));
+  HIPCHK(W.level_cnt.ensure(sizeof(int32_t) * lc.size()));
+  HIPCHK(W.hist.ensure(sizeof(uint32_t) * kHistBins * (size_t)n));
+  HIPCHK(W.goal_g.ensure(sizeof(int32_t) * (size_t)n));
+  HIPCHK(W.err.ensure(sizeof(int32_t)));
+  HIPCHK(hipMemcpyAsync(W.tree_off.p, off.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(W.level_cnt.p, lc.data(), sizeof(int32_t) * lc.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_zero_i32(W.err.as<int32_t>(), 1, st));
+  HIPCHK(launch_split4(W.inst.as<Inst>(), n, D, W.tree_off.as<int64_t>(), W.level_cnt.as<int32_t>(),
+                       W.tree.as<Node>(), W.hist.as<uint32_t>(), W.goal_g.as<int32_t>(),
+                       W.err.as<int32_t>(), st));
+
+  const int per_cu = batch4_max_blocks_per_cu(cap);
+  if (per_cu <= 0) return BPIDA_EDEVICE;
+  int64_t grid = (int64_t)per_cu * W.num_cu;
+  if (O.max_workgroups > 0) grid = std::min<int64_t>(grid, O.max_workgroups);
+  uint64_t qcap = 64;
+  const uint64_t want = O.queue_capacity > 0 ? (uint64_t)O.queue_capacity
+                                              : (uint64_t)(seed_chunks + grid * 16 + 1024);
+  while (qcap < want) qcap <<= 1;
+  HIPCHK(W.qctl.ensure(sizeof(QueueCtl)));
+  HIPCHK(W.qseq.ensure(sizeof(uint64_t) * qcap));
+  HIPCHK(W.qslots.ensure(sizeof(QChunk) * qcap));
+  HIPCHK(W.istate.ensure(sizeof(InstState) * (size_t)n));
+  HIPCHK(W.root_off.ensure(sizeof(int64_t) * (size_t)n));
+  HIPCHK(W.nroots.ensure(sizeof(int32_t) * (size_t)n));
+  HIPCHK(W.status.ensure(sizeof(int32_t) * (size_t)n));
+  HIPCHK(hipMemcpyAsync(W.root_off.p, root_off.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(W.nroots.p, nroots.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st));
+  HIPCHK(launch_zero_words(W.qctl.p, sizeof(QueueCtl), st));
+
+  BatchArgs A;
+  A.q = W.qctl.as<QueueCtl>();
+  A.seq = W.qseq.as<uint64_t>();
+  A.slots = W.qslots.as<QChunk>();
+  A.qmask = qcap - 1;
+  A.is = W.istate.as<InstState>();
+  A.tree = W.tree.as<Node>();
+  A.hist = W.hist.as<uint32_t>();
+  A.goal_g = W.goal_g.as<int32_t>();
+  A.out_len = d_len;
+  A.out_nodes = d_nodes;
+  A.n = n;
+  A.max_limit = (int)(O.max_threshold >= 0 ? std::min<int64_t>(O.max_threshold, kMaxLimit) : kMaxLimit);
+  A.idle_ticks = (uint64_t)O.watchdog_ms * (uint64_t)W.wall_khz;
+  A.budget_ticks = (uint64_t)O.budget_ms * (uint64_t)W.wall_khz;
+  HIPCHK(launch_batch_setup(A, W.inst.as<Inst>(), W.root_off.as<int64_t>(), W.nroots.as<int32_t>(), st));
+  HIPCHK(hipEventRecord(W.ev0, st));
+  HIPCHK(launch_batch4(cap, (int)grid, A, st));
+  HIPCHK(hipEventRecord(W.ev1, st));
+  HIPCHK(launch_batch_status(A.is, n, W.status.as<int32_t>(), st));
+  std::vector<int32_t> status((size_t)n);
+  QueueCtl qc;
+  int32_t split_err = 0;
+  HIPCHK(hipMemcpyAsync(status.data(), W.status.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&qc, W.qctl.p, sizeof(QueueCtl), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&split_err, W.err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, W.ev0, W.ev1) == hipSuccess) stats[4] = (uint64_t)(ms * 1000.0f);
+  stats[0] = qc.rounds;
+  stats[1] = qc.searched;
+  stats[2] = qc.pushes * kQChunk;
+  stats[3] = 1;
+  stats[6] = qc.pushes;
+  stats[7] = qc.pops;
+  stats[8] = qc.t_work / (uint64_t)std::max(1, W.wall_khz / 1000);  // microseconds
+  stats[9] = qc.t_queue / (uint64_t)std::max(1, W.wall_khz / 1000);
+  stats[10] = qc.t_idle / (uint64_t)std::max(1, W.wall_khz / 1000);
+  stats[11] = qc.voluntary;
+  stats[12] = (uint64_t)grid;
+  memcpy(g_stats, stats, sizeof stats);
+  if (split_err) return BPIDA_EINTERNAL;
+  // a full queue (1, 2, 16) is the root cause of anything that follows it
+  if (qc.err & (1 | 2 | 16)) return BPIDA_ENOMEM;
+  if (qc.err) return BPIDA_EINTERNAL;
+  int rc = BPIDA_OK;
+  for (int i = 0; i < n; ++i) {
+    const int s = status[i];
+    if (s != 1 && s != 0 && rc == BPIDA_OK) rc = s;
+    if (s == 0 && rc == BPIDA_OK) rc = BPIDA_EINTERNAL;  // never finished
+  }
+  return rc;
+#undef HIPCHK
+}
+
 int check_opts(int width) {
   if (width < BPIDA_MIN_WIDTH || width > BPIDA_MAX_WIDTH) return BPIDA_EINVAL;
   return BPIDA_OK;
@@ -319,8 +471,20 @@ extern "C" int bpida_set_option(const char* key, int64_t value) {
   if (!key) return BPIDA_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   const std::string k(key);
-  if (k == "frontier_depth") {
-    if (value < 0 || value > kMaxDepth) return BPIDA_EINVAL;
+  if (k == "mode") {
+    if (value != kModePlain && value != kModeBatched) return BPIDA_EINVAL;
+    g_opt.mode = value;
+  } else if (k == "budget_ms") {
+    if (value < 1 || value > 36000000) return BPIDA_EINVAL;
+    g_opt.budget_ms = value;
+  } else if (k == "watchdog_ms") {
+    if (value < 1 || value > 3600000) return BPIDA_EINVAL;
+    g_opt.watchdog_ms = value;
+  } else if (k == "queue_capacity") {
+    if (value < 0 || value > (int64_t(1) << 24)) return BPIDA_EINVAL;
+    g_opt.queue_capacity = value;
+  } else if (k == "frontier_depth") {
+    if (value < -1 || value > kMaxDepth) return BPIDA_EINVAL;
     g_opt.frontier_depth = value;
   } else if (k == "lds_stack_capacity") {
     if (value != 128 && value != 256 && value != 512 && value != 1024) return BPIDA_EINVAL;
@@ -344,6 +508,10 @@ extern "C" int64_t bpida_get_option(const char* key) {
   if (!key) return INT64_MIN;
   std::lock_guard<std::mutex> lk(g_mu);
   const std::string k(key);
+  if (k == "mode") return g_opt.mode;
+  if (k == "queue_capacity") return g_opt.queue_capacity;
+  if (k == "watchdog_ms") return g_opt.watchdog_ms;
+  if (k == "budget_ms") return g_opt.budget_ms;
   if (k == "frontier_depth") return g_opt.frontier_depth;
   if (k == "lds_stack_capacity") return g_opt.lds_stack_capacity;
   if (k == "spill_capacity") return g_opt.spill_capacity;
@@ -353,7 +521,7 @@ extern "C" int64_t bpida_get_option(const char* key) {
 }
 
 extern "C" int bpida_last_stats(uint64_t* out, int32_t n) {
-  if (!out || n < 0 || n > 8) return BPIDA_EINVAL;
+  if (!out || n < 0 || n > 16) return BPIDA_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   for (int i = 0; i < n; ++i) out[i] = g_stats[i];
   return BPIDA_OK;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace bpida {
 
 // ---------------------------------------------------------------------------
@@ -101,6 +103,70 @@ constexpr int kHistBins = 256;  // f values 0..255 of the split tree's interior
 constexpr int kMaxLimit = 255;  // slack and f fit in 8 bits
 constexpr int kMaxDepth = 16;  // deepest root split
 
+// ---------------------------------------------------------------------------
+// Batched persistent search (bpida_batch.hip).
+// ---------------------------------------------------------------------------
+constexpr int kQChunk = 64;  // stack entries per queue chunk
+
+// One queue slot: up to 64 stack entries of one instance at its current limit.
+struct alignas(128) QChunk {
+  uint64_t tiles[kQChunk];
+  uint16_t meta[kQChunk];
+  int32_t inst;
+  int32_t count;
+};
+
+// Per-instance search state.
+struct InstState {
+  int32_t limit;        // current f-limit
+  int32_t col;          // output column of the current limit
+  int32_t done;         // 0 searching, 1 solved, < 0 bpida_status
+  int32_t outstanding;  // chunks queued or held at the current limit
+  uint64_t nodes;       // nodes expanded by the search at the current limit
+  int32_t fmin;         // smallest pruned f at the current limit
+  int32_t goals;        // goals expanded at the current limit
+  int64_t root_off;     // first root of this instance in the split tree buffer
+  int32_t nroots;
+  int32_t pad;
+};
+
+// Queue control block and run counters.  The fields that many workgroups
+// touch concurrently sit on separate 128-byte lines.
+struct QueueCtl {
+  alignas(128) uint64_t head;
+  alignas(128) uint64_t tail;
+  alignas(128) int32_t remaining;  // instances still searching
+  alignas(128) int32_t err;  // 1: queue full while seeding, 2: entries dropped,
+                             // 4: idle watchdog, 8: deadline passed, 16: ring full
+  alignas(128) uint64_t rounds;
+  uint64_t searched, pushes, pops;
+  uint64_t t_work, t_queue, t_idle;  // wall-clock ticks summed over workgroups
+  uint64_t voluntary;                // donations made because workgroups idled
+};
+
+struct BatchArgs {
+  QueueCtl* q;
+  uint64_t* seq;       // per slot sequence number
+  QChunk* slots;
+  uint64_t qmask;      // capacity - 1 (capacity a power of two)
+  InstState* is;
+  const Node* tree;
+  const uint32_t* hist;
+  const int32_t* goal_g;
+  int32_t* out_len;
+  uint64_t* out_nodes;  // n x 64
+  int32_t n;
+  int32_t max_limit;
+  uint64_t idle_ticks;   // an idle workgroup gives up after this many wall-clock ticks
+  uint64_t budget_ticks; // every workgroup stops this many ticks after it starts
+};
+
+hipError_t launch_batch_setup(const BatchArgs& A, const Inst* d_inst, const int64_t* d_root_off,
+                              const int32_t* d_nroots, hipStream_t s);
+hipError_t launch_batch4(int lds_cap, int grid, const BatchArgs& A, hipStream_t s);
+hipError_t launch_batch_status(const InstState* d_is, int n, int32_t* d_status, hipStream_t s);
+int batch4_max_blocks_per_cu(int lds_cap);
+
 // Kernel launchers (bpida_kernels.hip).
 hipError_t launch_ingest4(const uint8_t* d_states, int n, Inst* d_inst, hipStream_t s);
 hipError_t launch_split4(const Inst* d_inst, int n, int depth, const int64_t* d_tree_off,
@@ -115,6 +181,7 @@ hipError_t launch_reduce(const Partial* d_part, int nwg, const uint32_t* d_hist_
 hipError_t launch_fill_outputs(int32_t* d_len, uint64_t* d_nodes, int n, hipStream_t s);
 hipError_t launch_set_len(int32_t* d_len_i, int32_t value, hipStream_t s);
 hipError_t launch_zero_i32(int32_t* d_p, int n, hipStream_t s);
+hipError_t launch_zero_words(void* d_p, size_t bytes, hipStream_t s);
 int search4_max_blocks_per_cu(int lds_cap);
 
 }  // namespace bpida

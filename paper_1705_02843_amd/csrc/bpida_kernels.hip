@@ -15,6 +15,7 @@
 #include <limits.h>
 
 #include "bpida_internal.h"
+#include "bpida_round.h"
 
 namespace bpida {
 
@@ -177,20 +178,7 @@ hipError_t launch_split4(const Inst* d_inst, int n, int depth, const int64_t* d_
 // ---------------------------------------------------------------------------
 constexpr int kChunk = 64;
 
-// Orders this wave's LDS accesses across lanes: LDS executes one wave's
-// operations in issue order, so a compiler-level barrier plus a wavefront
-// fence is all that is needed between a lane's store and another lane's load.
-#define WAVE_SYNC()                                      \
-  do {                                                   \
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); \
-    __builtin_amdgcn_wave_barrier();                     \
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
-  } while (0)
 
-__device__ __forceinline__ int wave_min(int v) {
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
-}
 
 template <int CAP>
 __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ roots, int nroots,
@@ -203,11 +191,7 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
   __shared__ uint16_t sm[CAP];
 
   const int lane = threadIdx.x;
-  const int e = lane >> 2;  // popped entry handled by this lane
-  const int a = lane & 3;   // move tried by this lane
-  const int delta = a == 0 ? -4 : a == 1 ? -1 : a == 2 ? 1 : 4;
-  const uint32_t sh = (a == 0 || a == 3) ? 2u : 0u;
-  const uint32_t tab = (uint32_t)(kDhTable4 >> (16 * a)) & 0xFFFFu;
+  const LaneMap M = make_lane_map(lane);
 
   uint64_t* sp_t = spill_tiles + (size_t)blockIdx.x * spill_cap;
   uint16_t* sp_m = spill_meta + (size_t)blockIdx.x * spill_cap;
@@ -261,44 +245,11 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
         avail -= kChunk;
         WAVE_SYNC();
       }
-      // parallelPop
+      // parallelPop + expand + atomicPut
       const int kp = min(avail, 16);
-      const int base = top - kp;
-      const int idx = (base + e) & (CAP - 1);
-      const uint64_t s = st[idx];
-      const uint32_t m = sm[idx];
-      const bool act = e < kp;
-      top = base;
+      top = bp_round<CAP>(st, sm, top, kp, limit, M, goals, fmin);
       expanded += (uint64_t)kp;
       rounds += 1;
-      // goal test on expansion (h == 0 <=> goal for Manhattan); counted and
-      // expanded like any node, its children all exceed the limit
-      goals += __popcll(__ballot(act && a == 0 && s == kGoal4));
-      // applicability: on the board and not undoing the parent move
-      const int b = (int)(m & 15u);
-      const int fb = (int)((m >> 4) & 7u);
-      const int slack = (int)(m >> 8);
-      const bool legal = act && ((kMoveMask4 >> (4 * b + a)) & 1ull) && a != fb;
-      // successor and incremental h: f_new <= limit <=> child slack >= 0
-      const int n = (b + delta) & 15;
-      const uint32_t t = (uint32_t)(s >> (4 * n)) & 15u;
-      const uint32_t up = (tab >> ((((t >> sh) & 3u) << 2) | (((uint32_t)n >> sh) & 3u))) & 1u;
-      const int slack2 = slack - 2 * (int)up;
-      const bool keep = legal && slack2 >= 0;
-      if (legal && slack2 < 0) fmin = min(fmin, limit - slack2);
-      const uint64_t cs = s + ((uint64_t)t << (4 * b)) - ((uint64_t)t << (4 * n));
-      const uint32_t cm = (uint32_t)n | ((uint32_t)(3 - a) << 4) | ((uint32_t)slack2 << 8);
-      // atomicPut: ballot + prefix count, one wave-wide step
-      const uint64_t km = __ballot(keep);
-      const int off = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
-                                                __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
-      if (keep) {
-        const int p = (top + off) & (CAP - 1);
-        st[p] = cs;
-        sm[p] = (uint16_t)cm;
-      }
-      top += __popcll(km);
-      WAVE_SYNC();
     }
   }
   fmin = wave_min(fmin);
@@ -465,6 +416,19 @@ __global__ void zero_i32_kernel(int32_t* p, int n) {
 hipError_t launch_zero_i32(int32_t* d_p, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d_p, n);
+  return hipGetLastError();
+}
+
+__global__ void zero_words_kernel(uint32_t* p, size_t n) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0u;
+}
+
+hipError_t launch_zero_words(void* d_p, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 4;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     (uint32_t*)d_p, n);
   return hipGetLastError();
 }
 

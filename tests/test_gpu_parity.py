@@ -30,10 +30,14 @@ def B():
     return bpida
 
 
+OPTION_KEYS = ("mode", "frontier_depth", "lds_stack_capacity", "spill_capacity",
+               "max_workgroups", "max_threshold", "queue_capacity", "watchdog_ms")
+MODES = {"plain": 0, "batched": 1}
+
+
 @pytest.fixture
 def opts(B):
-    keys = ("frontier_depth", "lds_stack_capacity", "spill_capacity", "max_workgroups",
-            "max_threshold")
+    keys = OPTION_KEYS
     saved = {k: B.get_option(k) for k in keys}
     yield B
     for k, v in saved.items():
@@ -66,16 +70,22 @@ def assert_parity(got_len, got_nodes, want_len, want_nodes, tag=""):
         got_nodes[bad[0], :12].tolist(), want_nodes[bad[0], :12].tolist())
 
 
-def test_walk40_64_instances_exact(B):
-    _say("case: c1_walk40 full, default options")
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_walk40_64_instances_exact(opts, mode):
+    B = opts
+    _say("case: c1_walk40 full, mode=%s" % mode)
+    B.set_option("mode", MODES[mode])
     states, want_len, want_nodes = load_golden("c1_walk40")
     rc, ln, nodes = B.solve_raw(states)
     assert rc == B.OK, B.strerror(rc)
     assert_parity(ln, nodes, want_len, want_nodes, "c1")
 
 
-def test_md30_38_100_instances_exact(B):
-    _say("case: c2_md30_38 full (100 instances, 2.2e10 nodes), default options")
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_md30_38_100_instances_exact(opts, mode):
+    B = opts
+    _say("case: c2_md30_38 full (100 instances, 2.2e10 nodes), mode=%s" % mode)
+    B.set_option("mode", MODES[mode])
     states, want_len, want_nodes = load_golden("c2_md30_38")
     rc, ln, nodes = B.solve_raw(states)
     assert rc == B.OK, B.strerror(rc)
@@ -84,10 +94,12 @@ def test_md30_38_100_instances_exact(B):
     _say("c2 stats: %s" % st)
 
 
+@pytest.mark.parametrize("mode", sorted(MODES))
 @pytest.mark.parametrize("depth", [0, 1, 2, 5, 8, 12])
-def test_split_depths_agree(opts, depth):
+def test_split_depths_agree(opts, depth, mode):
     B = opts
-    _say("case: c1 first 24, frontier_depth=%d" % depth)
+    _say("case: c1 first 24, frontier_depth=%d, mode=%s" % (depth, mode))
+    B.set_option("mode", MODES[mode])
     states, want_len, want_nodes = load_golden("c1_walk40")
     states, want_len, want_nodes = states[:24], want_len[:24], want_nodes[:24]
     B.set_option("frontier_depth", depth)
@@ -96,10 +108,12 @@ def test_split_depths_agree(opts, depth):
     assert_parity(ln, nodes, want_len, want_nodes, "D=%d" % depth)
 
 
+@pytest.mark.parametrize("mode", sorted(MODES))
 @pytest.mark.parametrize("cap", [128, 256, 1024])
-def test_lds_capacity_and_spill_agree(opts, cap):
+def test_lds_capacity_and_spill_agree(opts, cap, mode):
     B = opts
-    _say("case: c2 first 6, lds_stack_capacity=%d, depth 6" % cap)
+    _say("case: c2 6 instances, lds_stack_capacity=%d, depth 6, mode=%s" % (cap, mode))
+    B.set_option("mode", MODES[mode])
     states, want_len, want_nodes = load_golden("c2_md30_38")
     pick = [1, 4, 17, 26, 39, 77]
     states, want_len, want_nodes = states[pick], want_len[pick], want_nodes[pick]
@@ -112,10 +126,12 @@ def test_lds_capacity_and_spill_agree(opts, cap):
         assert B.last_stats()["spilled"] > 0  # the spill path was exercised
 
 
+@pytest.mark.parametrize("mode", sorted(MODES))
 @pytest.mark.parametrize("maxwg", [1, 7, 300])
-def test_grid_size_does_not_change_counts(opts, maxwg):
+def test_grid_size_does_not_change_counts(opts, maxwg, mode):
     B = opts
-    _say("case: c1 first 16, max_workgroups=%d" % maxwg)
+    _say("case: c1 first 16, max_workgroups=%d, mode=%s" % (maxwg, mode))
+    B.set_option("mode", MODES[mode])
     states, want_len, want_nodes = load_golden("c1_walk40")
     states, want_len, want_nodes = states[:16], want_len[:16], want_nodes[:16]
     B.set_option("max_workgroups", maxwg)
@@ -124,8 +140,10 @@ def test_grid_size_does_not_change_counts(opts, maxwg):
     assert_parity(ln, nodes, want_len, want_nodes, "maxwg=%d" % maxwg)
 
 
-def test_short_walks_goal_inside_split_tree(opts):
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_short_walks_goal_inside_split_tree(opts, mode):
     B = opts
+    B.set_option("mode", MODES[mode])
     from paper_1705_02843_amd import instances as I
     _say("case: walks of 0..14 moves, depth 10 (goal inside the split tree)")
     rng = np.random.Generator(np.random.PCG64(77))
@@ -137,8 +155,11 @@ def test_short_walks_goal_inside_split_tree(opts):
     assert_parity(ln, nodes, want.length, want.nodes, "short")
 
 
-def test_invalid_and_unsolvable_mixed_in(B):
-    _say("case: batch with invalid and unsolvable states")
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_invalid_and_unsolvable_mixed_in(opts, mode):
+    B = opts
+    B.set_option("mode", MODES[mode])
+    _say("case: batch with invalid and unsolvable states, mode=%s" % mode)
     states, want_len, want_nodes = load_golden("c1_walk40")
     s = states[:5].copy()
     s[1, 1], s[1, 2] = s[1, 2], s[1, 1]     # odd permutation: unsolvable
@@ -150,8 +171,13 @@ def test_invalid_and_unsolvable_mixed_in(B):
     assert_parity(ln[ok], nodes[ok], want_len[ok], want_nodes[ok], "mixed")
 
 
-def test_goal_and_one_move(B):
-    _say("case: goal state and one-move states")
+@pytest.mark.parametrize("mode", sorted(MODES))
+@pytest.mark.parametrize("depth", [0, 6])
+def test_goal_and_one_move(opts, mode, depth):
+    B = opts
+    B.set_option("mode", MODES[mode])
+    B.set_option("frontier_depth", depth)
+    _say("case: goal state and one-move states, mode=%s depth=%d" % (mode, depth))
     g = np.arange(16, dtype=np.uint8)
     r1 = g.copy(); r1[0], r1[1] = 1, 0
     d1 = g.copy(); d1[0], d1[4] = 4, 0
@@ -161,9 +187,11 @@ def test_goal_and_one_move(B):
     assert nodes[:, 0].tolist() == [1, 2, 2] and (nodes[:, 1:] == 0).all()
 
 
-def test_limit_cap_keeps_completed_counts(opts):
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_limit_cap_keeps_completed_counts(opts, mode):
     B = opts
-    _say("case: max_threshold cap")
+    B.set_option("mode", MODES[mode])
+    _say("case: max_threshold cap, mode=%s" % mode)
     states, want_len, want_nodes = load_golden("c1_walk40")
     s = states[:4]
     h0 = [int(want_len[i]) for i in range(4)]
@@ -179,9 +207,12 @@ def test_limit_cap_keeps_completed_counts(opts):
     del h0
 
 
-def test_device_entry_on_torch_stream(B):
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_device_entry_on_torch_stream(opts, mode):
     import torch
-    _say("case: bpida_solve_device on a side stream")
+    B = opts
+    B.set_option("mode", MODES[mode])
+    _say("case: bpida_solve_device on a side stream, mode=%s" % mode)
     states, want_len, want_nodes = load_golden("c1_walk40")
     d_states = torch.from_numpy(states).cuda()
     d_len = torch.full((64,), -9, dtype=torch.int32, device="cuda")
@@ -198,3 +229,31 @@ def test_device_entry_on_torch_stream(B):
 def test_empty_batch(B):
     rc, ln, nodes = B.solve_raw(np.zeros((0, 16), np.uint8))
     assert rc == B.OK and ln.size == 0
+
+
+def test_batched_queue_too_small_reports_enomem(opts):
+    B = opts
+    _say("case: batched, one workgroup, 64-chunk queue, 3 instances at depth 12 (~700 seed chunks)")
+    B.set_option("mode", 1)
+    B.set_option("frontier_depth", 12)
+    B.set_option("queue_capacity", 64)
+    B.set_option("max_workgroups", 1)
+    B.set_option("watchdog_ms", 300)
+    states, _, _ = load_golden("c1_walk40")
+    rc, ln, nodes = B.solve_raw(states[:3])
+    assert rc == B.ENOMEM
+
+
+def test_batched_uneven_batch_exact(opts):
+    """Instances of very different depths in one persistent launch."""
+    B = opts
+    from paper_1705_02843_amd import instances as I
+    _say("case: batched, 96 walks of length U{20..120}, max Manhattan 30")
+    states, _ = I.walks_uniform_len(96, 4, 20, 120, 30, 31)
+    want = oracle_expect(states)
+    B.set_option("mode", 1)
+    rc, ln, nodes = B.solve_raw(states)
+    assert rc == B.OK
+    assert_parity(ln, nodes, want.length, want.nodes, "uneven")
+    st = B.last_stats()
+    _say("stats: %s" % st)
