@@ -38,9 +38,10 @@ OPS_PER_NODE = 64
 
 WORKLOADS = {
     "c2_md30_38": ("100 15-puzzle states from seeded 300-move non-backtracking walks, Manhattan "
-                   "30..38; plain BPIDA*: one instance per launch sequence", 4),
-    "c1_walk40": ("64 15-puzzle states from seeded 40-move non-backtracking walks; plain BPIDA*", 4),
+                   "30..38, all-optimal-solutions final limit", 4),
+    "c1_walk40": ("64 15-puzzle states from seeded 40-move non-backtracking walks", 4),
 }
+MODES = {"plain": 0, "batched": 1}
 
 
 def kernel_source_hash() -> str:
@@ -92,10 +93,11 @@ def cpu_baseline(name, states, budget_nodes, nthreads):
                 len(pick), r.total_nodes, dt, nthreads)}
 
 
-def load_traffic(src_hash):
-    """Per-launch HBM bytes of the search kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "search4_c2_md30_38_traffic.json")
+def load_traffic(src_hash, mode):
+    """Per-launch HBM bytes of the timed search kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "%s_c2_md30_38_traffic.json" % (
+        "batch4" if mode == "batched" else "search4"))
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -113,6 +115,11 @@ def main():
     ap.add_argument("--workload", default="c2_md30_38", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget-nodes", type=float, default=4e9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="batched", choices=sorted(MODES),
+                    help="path timed for `value` (batched: one persistent launch with a device "
+                         "work queue; plain: one launch per instance and f-limit)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip timing the other mode beside it")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -144,43 +151,46 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
-    def step():
-        rc = bpida.solve_device(d_states, d_len, d_nodes, width=width, stream=stream)
-        if rc != bpida.OK:
-            raise bpida.BpidaError(rc, "bpida_solve_device")
+    def run_mode(mode, steps, warmup):
+        bpida.set_option("mode", MODES[mode])
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+        def step():
+            rc = bpida.solve_device(d_states, d_len, d_nodes, width=width, stream=stream)
+            if rc != bpida.OK:
+                raise bpida.BpidaError(rc, "bpida_solve_device")
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        acc = {}
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+            for k, v in bpida.last_stats().items():
+                acc[k] = acc.get(k, 0) + v
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        nodes_step = int(d_nodes.cpu().numpy().view(np.uint64).sum(dtype=np.uint64))
+        if expect is not None and nodes_step != expect:
+            raise SystemExit("%s: node total %d differs from the stored oracle total %d" % (
+                mode, nodes_step, expect))
+        assert (d_len.cpu().numpy() >= 0).all()
+        return dt, nodes_step, acc
+
     expect = golden_total(args.workload)
-    nodes_per_step = None
-    search_nodes = search_us = launches = rounds = spilled = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-        st = bpida.last_stats()
-        search_nodes += st["search_nodes"]
-        search_us += st["search_us"]
-        launches += st["launches"]
-        rounds += st["rounds"]
-        spilled += st["spilled"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-
-    nodes_per_step = int(d_nodes.cpu().numpy().view(np.uint64).sum(dtype=np.uint64))
-    lens = d_len.cpu().numpy()
-    if expect is not None and nodes_per_step != expect:
-        raise SystemExit("node total %d differs from the stored oracle total %d" % (nodes_per_step,
-                                                                                    expect))
-    assert (lens >= 0).all()
+    dt, nodes_per_step, acc = run_mode(args.mode, args.steps, args.warmup)
+    search_nodes, search_us, launches = acc["search_nodes"], acc["search_us"], acc["launches"]
+    rounds = acc["rounds"]
     total_nodes = nodes_per_step * args.steps
     value = total_nodes / dt
     avg_launch_s = (search_us / launches) * 1e-6 if launches else float("nan")
     ops_per_launch = search_nodes * OPS_PER_NODE / launches if launches else 0.0
     achieved = ops_per_launch / avg_launch_s / 1e9 if launches else 0.0
     src_hash = kernel_source_hash()
-    traffic = load_traffic(src_hash)
+    traffic = load_traffic(src_hash, args.mode)
+    cap = bpida.get_option("lds_stack_capacity")
+    kname = ("batch4_kernel<%d>" if args.mode == "batched" else "search4_kernel<%d>") % cap
+    wg_total = acc.get("wg_us_search", 0) + acc.get("wg_us_queue", 0) + acc.get("wg_us_idle", 0)
 
     out = {
         "metric": METRIC,
@@ -196,7 +206,7 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n_instances": n,
-                   "mode": "plain",
+                   "mode": args.mode,
                    "frontier_depth": bpida.get_option("frontier_depth"),
                    "lds_stack_capacity": bpida.get_option("lds_stack_capacity")},
         "instances_per_s": round(n * args.steps / dt, 2),
@@ -204,7 +214,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 1), "peak": round(PEAK_INT_GOPS, 1),
                      "unit": "Gop/s", "frac": round(achieved / PEAK_INT_GOPS, 4),
                      "traffic": traffic,
-                     "kernel": "search4_kernel<%d>" % bpida.get_option("lds_stack_capacity"),
+                     "kernel": kname,
                      "ops_per_node": OPS_PER_NODE,
                      "avg_launch_us": round(avg_launch_s * 1e6, 2),
                      "launches_per_step": launches // max(1, args.steps),
@@ -212,9 +222,21 @@ def main():
                      if search_us else None},
         "search_rounds_per_step": rounds // max(1, args.steps),
         "pop_occupancy": round(search_nodes / (16.0 * rounds), 4) if rounds else None,
-        "spilled_per_step": spilled // max(1, args.steps),
         "kernel_source_hash": src_hash,
     }
+    if args.mode == "batched" and wg_total:
+        out["batched"] = {"grid": acc["grid"] // max(1, args.steps),
+                          "busy_frac": round(acc["wg_us_search"] / wg_total, 4),
+                          "queue_frac": round(acc["wg_us_queue"] / wg_total, 4),
+                          "chunks_donated_per_step": acc["chunks_pushed"] // max(1, args.steps)}
+    if not args.no_compare:
+        other = "plain" if args.mode == "batched" else "batched"
+        odt, _, _ = run_mode(other, 1, 1)
+        out["compare"] = {"mode": other, "value": round(nodes_per_step / odt, 1),
+                          "unit": "nodes/s", "ms_per_step": round(odt * 1e3, 3),
+                          "instances_per_s": round(n / odt, 2), "steps": 1, "warmup": 1,
+                          "speedup_of_value": round((nodes_per_step / odt) and value / (nodes_per_step / odt), 3)}
+        bpida.set_option("mode", MODES[args.mode])
     if not args.no_cpu_baseline:
         nthreads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(args.workload, states, args.cpu_budget_nodes, nthreads)
