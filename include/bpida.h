@@ -88,6 +88,24 @@ int bpida_solve_device(const uint8_t *d_states, int32_t n_instances, int32_t wid
                        int32_t *d_len, uint64_t *d_nodes, void *hip_stream);
 
 /*
+ * Enqueue a batched solve (mode option ignored: always the persistent
+ * launch) on `hip_stream` and return without waiting: no host
+ * synchronisation and no copy to the host, so the call can be recorded into a
+ * HIP graph and replayed.  Buffers as in bpida_solve_device, plus d_status
+ * (device, n int32): 1 = solved, otherwise a negative bpida_status for that
+ * instance (a queue overflow marks every instance BPIDA_ENOMEM).  The
+ * library's device workspace is sized on the first call for a given n and
+ * options and then reused; a call that would have to grow it while the stream
+ * is capturing returns BPIDA_EINVAL (make one uncaptured call first).
+ * Returns BPIDA_OK once the work is enqueued, or an argument/device error.
+ * Concurrent solves on one device share the workspace: calls are serialised,
+ * but enqueued work from two calls must not overlap on different streams.
+ */
+int bpida_solve_device_async(const uint8_t *d_states, int32_t n_instances, int32_t width,
+                             int32_t *d_len, uint64_t *d_nodes, int32_t *d_status,
+                             void *hip_stream);
+
+/*
  * Set a tuning or control option for subsequent calls (process-wide).
  *   "mode"               1 = batched (default): one persistent launch searches
  *                        all instances through all limits from a device work
@@ -98,16 +116,25 @@ int bpida_solve_device(const uint8_t *d_states, int32_t n_instances, int32_t wid
  *   "frontier_depth"     depth D of the root split, 0..16, or -1 (default):
  *                        10 in plain mode, 6 in batched mode
  *   "lds_stack_capacity" DFS stack entries per workgroup in LDS: 128, 256,
- *                        512 or 1024 (default 512); deeper entries spill
+ *                        512, 1024 or 2048, or -1 (default): 512 for 16-node
+ *                        rounds, 1024 for 64-node rounds (64-node rounds need
+ *                        at least 512; smaller is BPIDA_EINVAL at solve time);
+ *                        deeper entries spill to HBM (plain) or to the work
+ *                        queue (batched)
+ *   "nodes_per_round"    batched mode: 64 (default) pops one node per lane and
+ *                        each lane tries the four moves; 16 uses Alg. 1's map
+ *                        (lane l expands node l/4 with move l%4).  Plain mode
+ *                        always uses 16.
  *   "spill_capacity"     plain mode: per-workgroup HBM spill entries, a
  *                        multiple of 64 (default 16384)
  *   "queue_capacity"     batched mode: queue slots of 64 entries (rounded up
  *                        to a power of two, at least 64; 0 = sized from the
  *                        batch); a queue that stays full while a workgroup
  *                        pushes makes the call return BPIDA_ENOMEM
- *   "watchdog_ms"        batched mode: a workgroup that finds no work for
- *                        this long while instances remain stops and the call
- *                        returns BPIDA_EINTERNAL (default 20000)
+ *   "watchdog_ms"        batched mode: an idle workgroup that sees no work
+ *                        queue activity for this long while instances remain
+ *                        stops and the call returns BPIDA_EINTERNAL (default
+ *                        20000)
  *   "budget_ms"          batched mode: every workgroup of the persistent launch
  *                        stops after this long and the call returns
  *                        BPIDA_EINTERNAL (default 600000)

@@ -17,8 +17,8 @@ OK, EINVAL, EUNSOLVABLE, ELIMIT, ENOMEM, EDEVICE, EINTERNAL = 0, -1, -2, -3, -4,
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbpida.so")
 
-EXPORTS = ("bpida_solve", "bpida_solve_device", "bpida_set_option", "bpida_get_option",
-           "bpida_last_stats", "bpida_strerror")
+EXPORTS = ("bpida_solve", "bpida_solve_device", "bpida_solve_device_async", "bpida_set_option",
+           "bpida_get_option", "bpida_last_stats", "bpida_strerror")
 
 
 class BpidaError(RuntimeError):
@@ -39,6 +39,10 @@ def _load() -> ctypes.CDLL:
     lib.bpida_solve_device.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.bpida_solve_device.restype = ctypes.c_int
+    lib.bpida_solve_device_async.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]
+    lib.bpida_solve_device_async.restype = ctypes.c_int
     lib.bpida_set_option.argtypes = [ctypes.c_char_p, ctypes.c_int64]
     lib.bpida_set_option.restype = ctypes.c_int
     lib.bpida_get_option.argtypes = [ctypes.c_char_p]
@@ -116,3 +120,23 @@ def solve_device(d_states, d_len, d_nodes, width: int = 4, stream=None) -> int:
                                       ctypes.c_void_p(d_len.data_ptr()),
                                       ctypes.c_void_p(d_nodes.data_ptr()),
                                       ctypes.c_void_p(s.cuda_stream)))
+
+
+def solve_device_async(d_states, d_len, d_nodes, d_status, width: int = 4, stream=None) -> int:
+    """Enqueue a batched solve on torch tensors without waiting (capturable
+    into a graph); per-instance status goes to ``d_status`` (int32 [n])."""
+    import torch  # device buffers and streams only
+
+    n = int(d_states.shape[0])
+    assert d_states.is_cuda and d_states.dtype == torch.uint8 and d_states.is_contiguous()
+    assert d_states.numel() == n * width * width
+    assert d_len.is_cuda and d_len.dtype == torch.int32 and d_len.numel() >= n
+    assert d_status.is_cuda and d_status.dtype == torch.int32 and d_status.numel() >= n
+    assert d_nodes.is_cuda and d_nodes.dtype in (torch.int64, torch.uint64)
+    assert d_nodes.is_contiguous() and d_nodes.numel() >= n * MAX_THRESHOLDS
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(lib.bpida_solve_device_async(ctypes.c_void_p(d_states.data_ptr()), n, width,
+                                            ctypes.c_void_p(d_len.data_ptr()),
+                                            ctypes.c_void_p(d_nodes.data_ptr()),
+                                            ctypes.c_void_p(d_status.data_ptr()),
+                                            ctypes.c_void_p(s.cuda_stream)))

@@ -251,9 +251,15 @@ __device__ void release_unit(const BatchArgs& A, int i, uint64_t expanded, int g
 // ---------------------------------------------------------------------------
 // The persistent kernel.
 // ---------------------------------------------------------------------------
-template <int CAP>
+// NPL = nodes popped per round: 16 (lane l expands node l/4 with move l%4,
+// Alg. 1's thread -> action map) or 64 (one node per lane, four moves each).
+template <int CAP, int NPL>
 __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
   static_assert((CAP & (CAP - 1)) == 0 && CAP >= 128, "ring size");
+  static_assert(NPL == 16 || NPL == 64, "nodes per round");
+  static_assert(NPL == 16 || CAP >= 512, "ring too small for 64-node rounds");
+  // largest growth of one round: a popped node has at most 4 children
+  constexpr int kGrow = NPL == 16 ? 32 : 3 * 64;
   __shared__ uint64_t st[CAP];
   __shared__ uint16_t sm[CAP];
   const int lane = threadIdx.x;
@@ -271,7 +277,8 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
   uint64_t t_mark = wall_clock64();
   int inst = -1, limit = 0;
   uint64_t expanded = 0;
-  int goals = 0, fmin = INT_MAX;
+  int goals = 0, fmin = INT_MAX;  // 16-node rounds track fmin per lane
+  int smax = INT_MIN;             // 64-node rounds track the largest pruned slack
   int top = 0, bot = 0;
   bool idle = false;
   uint64_t idle_since = 0, idle_act = 0;
@@ -288,6 +295,10 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
         t_mark = now;
       }
       if (inst >= 0) {
+        if (NPL == 64) {
+          const int sm_w = wave_max(smax);
+          fmin = sm_w == INT_MIN ? INT_MAX : limit - sm_w;
+        }
         release_unit(A, inst, expanded, goals, fmin);
         searched += expanded;
         inst = -1;
@@ -342,6 +353,7 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
       expanded = 0;
       goals = 0;
       fmin = INT_MAX;
+      smax = INT_MIN;
       top = cnt;
       bot = 0;
       if (lane < cnt) {
@@ -356,7 +368,7 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
       if (lane == 0) atomicOr(&q->err, 8);
       break;  // abandon: the call reports BPIDA_EINTERNAL
     }
-    if (avail + 32 > CAP) {
+    if (avail + kGrow > CAP) {
       // LDS would overflow: move the 64 oldest entries to the queue
       const int p = (bot + lane) & (CAP - 1);
       const uint64_t t = st[p];
@@ -409,8 +421,9 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
         }
       }
     }
-    const int kp = min(avail, 16);
-    top = bp_round<CAP>(st, sm, top, kp, limit, M, goals, fmin);
+    const int kp = min(avail, NPL);
+    if (NPL == 16) top = bp_round<CAP>(st, sm, top, kp, limit, M, goals, fmin);
+    else top = bp_round64<CAP>(st, sm, top, kp, goals, smax);
     expanded += (uint64_t)kp;
     rounds += 1;
   }
@@ -452,9 +465,20 @@ __global__ void batch_setup_kernel(BatchArgs A, const Inst* __restrict__ inst,
   }
 }
 
-__global__ void batch_status_kernel(const InstState* __restrict__ is, int n, int32_t* __restrict__ st) {
+// Per-instance status: 1 solved, < 0 a bpida_status.  A failed split or a
+// queue that overflowed (its dropped work invalidates every count) marks
+// every instance; a watchdog or deadline stop marks the unfinished ones.
+__global__ void batch_status_kernel(const InstState* __restrict__ is, int n,
+                                    const QueueCtl* __restrict__ q,
+                                    const int32_t* __restrict__ split_err, int32_t* __restrict__ st) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) st[k] = is[k].done;
+  if (k >= n) return;
+  const int32_t done = is[k].done;
+  int32_t v = done;
+  if (*split_err) v = -6;                    // BPIDA_EINTERNAL
+  else if (q->err & (1 | 2 | 16)) v = -4;   // BPIDA_ENOMEM
+  else if (done == 0) v = -6;               // stopped by the watchdog or the deadline
+  st[k] = v;
 }
 
 hipError_t launch_batch_setup(const BatchArgs& A, const Inst* d_inst, const int64_t* d_root_off,
@@ -465,40 +489,47 @@ hipError_t launch_batch_setup(const BatchArgs& A, const Inst* d_inst, const int6
   return hipGetLastError();
 }
 
-hipError_t launch_batch_status(const InstState* d_is, int n, int32_t* d_status, hipStream_t s) {
+hipError_t launch_batch_status(const InstState* d_is, int n, const QueueCtl* d_q,
+                               const int32_t* d_split_err, int32_t* d_status, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(batch_status_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d_is, n, d_status);
+  hipLaunchKernelGGL(batch_status_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d_is, n, d_q,
+                     d_split_err, d_status);
   return hipGetLastError();
 }
 
-template <int CAP>
+template <int CAP, int NPL>
 static hipError_t launch_batch_t(int grid, const BatchArgs& A, hipStream_t s) {
-  hipLaunchKernelGGL(batch4_kernel<CAP>, dim3(grid), dim3(64), 0, s, A);
+  hipLaunchKernelGGL((batch4_kernel<CAP, NPL>), dim3(grid), dim3(64), 0, s, A);
   return hipGetLastError();
 }
 
-hipError_t launch_batch4(int lds_cap, int grid, const BatchArgs& A, hipStream_t s) {
-  if (grid <= 0) return hipSuccess;
-  switch (lds_cap) {
-    case 128: return launch_batch_t<128>(grid, A, s);
-    case 256: return launch_batch_t<256>(grid, A, s);
-    case 512: return launch_batch_t<512>(grid, A, s);
-    case 1024: return launch_batch_t<1024>(grid, A, s);
-    default: return hipErrorInvalidValue;
-  }
+template <int CAP, int NPL>
+static int occupancy_t() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch4_kernel<CAP, NPL>, 64, 0) != hipSuccess)
+    return 0;
+  return nb;
 }
 
-int batch4_max_blocks_per_cu(int lds_cap) {
-  int nb = 0;
-  hipError_t e = hipErrorInvalidValue;
-  switch (lds_cap) {
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch4_kernel<128>, 64, 0); break;
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch4_kernel<256>, 64, 0); break;
-    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch4_kernel<512>, 64, 0); break;
-    case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch4_kernel<1024>, 64, 0); break;
-    default: break;
-  }
-  return e == hipSuccess ? nb : 0;
+// Supported (ring capacity, nodes per round) pairs.
+#define BATCH_CONFIGS(X) \
+  X(128, 16) X(256, 16) X(512, 16) X(1024, 16) X(2048, 16) X(512, 64) X(1024, 64) X(2048, 64)
+
+hipError_t launch_batch4(int lds_cap, int npl, int grid, const BatchArgs& A, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+#define X(C, N) \
+  if (lds_cap == C && npl == N) return launch_batch_t<C, N>(grid, A, s);
+  BATCH_CONFIGS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+int batch4_max_blocks_per_cu(int lds_cap, int npl) {
+#define X(C, N) \
+  if (lds_cap == C && npl == N) return occupancy_t<C, N>();
+  BATCH_CONFIGS(X)
+#undef X
+  return 0;
 }
 
 }  // namespace bpida

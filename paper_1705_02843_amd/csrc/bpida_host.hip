@@ -26,10 +26,11 @@ enum { kModePlain = 0, kModeBatched = 1 };
 struct Options {
   int64_t mode = kModeBatched;
   int64_t frontier_depth = -1;  // -1: 10 for plain, 6 for batched
+  int64_t nodes_per_round = 64; // batched mode: 16 (4 lanes per node) or 64
   int64_t queue_capacity = 0;   // chunks; 0: sized from the batch
   int64_t watchdog_ms = 20000;  // idle workgroups give up after this long
   int64_t budget_ms = 600000;   // the persistent launch stops after this long
-  int64_t lds_stack_capacity = 512;
+  int64_t lds_stack_capacity = -1;  // -1: 512 for 16-node rounds, 1024 for 64
   int64_t spill_capacity = 16384;
   int64_t max_workgroups = 0;
   int64_t max_threshold = -1;
@@ -39,12 +40,16 @@ std::mutex g_mu;  // serialises solves and option changes
 Options g_opt;
 uint64_t g_stats[16] = {0};
 
+// Set while the caller's stream is capturing a graph: buffers may not grow.
+bool g_no_alloc = false;
+
 // Grow-only device buffer.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   hipError_t ensure(size_t want) {
     if (want <= bytes) return hipSuccess;
+    if (g_no_alloc) return hipErrorInvalidValue;
     if (p) {
       hipError_t e = hipFree(p);
       if (e != hipSuccess) return e;
@@ -72,8 +77,9 @@ struct Workspace {
   int num_cu = 0;
   int wall_khz = 100000;
   bool arch_ok = false;
-  DevBuf inst, tree, tree_off, level_cnt, hist, goal_g, err, cursor, part, spill_t, spill_m, res;
-  DevBuf qctl, qseq, qslots, istate, root_off, nroots, status;
+  DevBuf inst, tree, tree_off, hist, goal_g, err, cursor, part, spill_t, spill_m, res;
+  DevBuf qctl, qseq, qslots, istate, root_off, nroots, status, walks;
+  int32_t h_walks[16][kMaxDepth + 1];  // non-backtracking walk counts per start cell and length
   DevBuf h2d_states, out_len, out_nodes;
   LimitResult* h_res = nullptr;  // pinned
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -85,6 +91,29 @@ int map_err(hipError_t e) {
   if (e == hipSuccess) return BPIDA_OK;
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return BPIDA_ENOMEM;
   return BPIDA_EDEVICE;
+}
+
+// Number of non-backtracking blank walks of each length 0..depth from `blank`
+// (the exact size of each level of the split tree).
+void level_sizes(int blank, int depth, int32_t* out) {
+  int64_t cur[16][5] = {};
+  cur[blank][4] = 1;
+  for (int d = 0; d <= depth; ++d) {
+    int64_t tot = 0, nxt[16][5] = {};
+    for (int c = 0; c < 16; ++c)
+      for (int fb = 0; fb < 5; ++fb) {
+        const int64_t m = cur[c][fb];
+        if (!m) continue;
+        tot += m;
+        for (int a = 0; a < 4; ++a) {
+          if (!((kMoveMask4 >> (4 * c + a)) & 1ull) || a == fb) continue;
+          const int n = c + (a == 0 ? -4 : a == 1 ? -1 : a == 2 ? 1 : 4);
+          nxt[n][3 - a] += m;
+        }
+      }
+    out[d] = (int32_t)tot;
+    memcpy(cur, nxt, sizeof cur);
+  }
 }
 
 int ensure_device() {
@@ -111,30 +140,16 @@ int ensure_device() {
     return BPIDA_ENOMEM;
   if (hipEventCreate(&g_ws.ev0) != hipSuccess || hipEventCreate(&g_ws.ev1) != hipSuccess)
     return BPIDA_EDEVICE;
+  for (int c = 0; c < 16; ++c) level_sizes(c, kMaxDepth, g_ws.h_walks[c]);
+  if (g_ws.walks.ensure(sizeof g_ws.h_walks) != hipSuccess) return BPIDA_ENOMEM;
+  if (hipMemcpy(g_ws.walks.p, g_ws.h_walks, sizeof g_ws.h_walks, hipMemcpyHostToDevice) != hipSuccess)
+    return BPIDA_EDEVICE;
   return BPIDA_OK;
 }
 
-// Number of non-backtracking blank walks of each length 0..depth from `blank`
-// (the exact size of each level of the split tree).
-void level_sizes(int blank, int depth, int32_t* out) {
-  int64_t cur[16][5] = {};
-  cur[blank][4] = 1;
-  for (int d = 0; d <= depth; ++d) {
-    int64_t tot = 0, nxt[16][5] = {};
-    for (int c = 0; c < 16; ++c)
-      for (int fb = 0; fb < 5; ++fb) {
-        const int64_t m = cur[c][fb];
-        if (!m) continue;
-        tot += m;
-        for (int a = 0; a < 4; ++a) {
-          if (!((kMoveMask4 >> (4 * c + a)) & 1ull) || a == fb) continue;
-          const int n = c + (a == 0 ? -4 : a == 1 ? -1 : a == 2 ? 1 : 4);
-          nxt[n][3 - a] += m;
-        }
-      }
-    out[d] = (int32_t)tot;
-    memcpy(cur, nxt, sizeof cur);
-  }
+int cap_for(const Options& O, int npl) {
+  if (O.lds_stack_capacity > 0) return (int)O.lds_stack_capacity;
+  return npl == 64 ? 1024 : 512;
 }
 
 int depth_for(const Options& O) {
@@ -166,7 +181,7 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
   HIPCHK(launch_fill_outputs(d_len, d_nodes, n, st));
   if (n == 0) return BPIDA_OK;
   const int D = depth_for(O);
-  const int cap = (int)O.lds_stack_capacity;
+  const int cap = cap_for(O, 16);
   const int spill_cap = (int)O.spill_capacity;
 
   // a1: ingest
@@ -194,16 +209,14 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
   }
   HIPCHK(W.tree.ensure(sizeof(Node) * (size_t)off[n]));
   HIPCHK(W.tree_off.ensure(sizeof(int64_t) * (size_t)n));
-  HIPCHK(W.level_cnt.ensure(sizeof(int32_t) * lc.size()));
   HIPCHK(W.hist.ensure(sizeof(uint32_t) * kHistBins * (size_t)n));
   HIPCHK(W.goal_g.ensure(sizeof(int32_t) * (size_t)n));
   HIPCHK(W.err.ensure(sizeof(int32_t)));
   HIPCHK(hipMemcpyAsync(W.tree_off.p, off.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(W.level_cnt.p, lc.data(), sizeof(int32_t) * lc.size(), hipMemcpyHostToDevice, st));
   HIPCHK(launch_zero_i32(W.err.as<int32_t>(), 1, st));
-  HIPCHK(launch_split4(W.inst.as<Inst>(), n, D, W.tree_off.as<int64_t>(), W.level_cnt.as<int32_t>(),
+  HIPCHK(launch_split4(W.inst.as<Inst>(), n, D, W.tree_off.as<int64_t>(), 0, W.walks.as<int32_t>(),
                        W.tree.as<Node>(), W.hist.as<uint32_t>(), W.goal_g.as<int32_t>(),
-                       W.err.as<int32_t>(), st));
+                       W.err.as<int32_t>(), nullptr, nullptr, st));
   int32_t split_err = 0;
   HIPCHK(hipMemcpyAsync(&split_err, W.err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -211,7 +224,7 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
 
   // a4..a9: persistent search grid and its scratch
   int per_cu = search4_max_blocks_per_cu(cap);
-  if (per_cu <= 0) return BPIDA_EDEVICE;
+  if (per_cu <= 0) return BPIDA_EINVAL;
   int64_t max_grid = (int64_t)per_cu * W.num_cu;
   if (O.max_workgroups > 0) max_grid = std::min<int64_t>(max_grid, O.max_workgroups);
   HIPCHK(W.part.ensure(sizeof(Partial) * (size_t)max_grid));
@@ -275,12 +288,13 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
   return rc;
 }
 
-// The batched driver: one persistent launch searches every instance through
-// all of its limits (device work queue, donation, device-side limit advance).
-int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes, hipStream_t st,
-                const Options& O) {
+// Enqueues the whole batched solve on `st`; per-instance status (1 solved,
+// < 0 bpida_status) lands in d_status.  No host synchronisation, no copy to
+// the host: the sequence can be recorded into a HIP graph.
+int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
+                    int32_t* d_status, hipStream_t st, const Options& O, bool timed,
+                    int64_t* grid_out) {
   Workspace& W = g_ws;
-  uint64_t stats[16] = {0};
   hipError_t e;
 #define HIPCHK(x)              \
   do {                         \
@@ -294,46 +308,36 @@ int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_node
   HIPCHK(launch_fill_outputs(d_len, d_nodes, n, st));
   if (n == 0) return BPIDA_OK;
   const int D = depth_for(O);
-  const int cap = (int)O.lds_stack_capacity;
+  const int npl = (int)O.nodes_per_round;
+  const int cap = cap_for(O, npl);
+  if (n == 0) return BPIDA_OK;
 
-  HIPCHK(W.inst.ensure(sizeof(Inst) * (size_t)n));
-  HIPCHK(launch_ingest4(d_states, n, W.inst.as<Inst>(), st));
-  std::vector<Inst> inst((size_t)n);
-  HIPCHK(hipMemcpyAsync(inst.data(), W.inst.p, sizeof(Inst) * (size_t)n, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-
-  const int L1 = kMaxDepth + 1;
-  std::vector<int32_t> lc((size_t)n * L1, 0), nroots((size_t)n, 0);
-  std::vector<int64_t> off((size_t)n + 1, 0), root_off((size_t)n, 0);
-  int64_t seed_chunks = 0;
-  for (int i = 0; i < n; ++i) {
-    int32_t* row = lc.data() + (size_t)i * L1;
-    if (inst[i].status == 0) level_sizes(inst[i].blank, D, row);
-    else row[0] = 1;
+  // Every buffer size below depends on n and D only, and no value travels
+  // back to the host before the persistent launch: the whole solve is one
+  // stream-ordered sequence of kernels.
+  int64_t stride = 0, max_roots = 0;
+  for (int c = 0; c < 16; ++c) {
     int64_t tot = 0;
-    for (int d = 0; d <= D; ++d) {
-      if (d == D) root_off[i] = off[i] + tot;
-      tot += row[d];
-    }
-    off[i + 1] = off[i] + tot;
-    nroots[i] = inst[i].status == 0 ? row[D] : 0;
-    seed_chunks += (nroots[i] + kQChunk - 1) / kQChunk;
+    for (int d = 0; d <= D; ++d) tot += W.h_walks[c][d];
+    stride = std::max(stride, tot);
+    max_roots = std::max<int64_t>(max_roots, W.h_walks[c][D]);
   }
-  HIPCHK(W.tree.ensure(sizeof(Node) * (size_t)off[n]));
-  HIPCHK(W.tree_off.ensure(sizeof(int64_t) * (size_t)n));
-  HIPCHK(W.level_cnt.ensure(sizeof(int32_t) * lc.size()));
+  const int64_t seed_chunks = (int64_t)n * ((max_roots + kQChunk - 1) / kQChunk);
+  HIPCHK(W.inst.ensure(sizeof(Inst) * (size_t)n));
+  HIPCHK(W.tree.ensure(sizeof(Node) * (size_t)(stride * n)));
   HIPCHK(W.hist.ensure(sizeof(uint32_t) * kHistBins * (size_t)n));
   HIPCHK(W.goal_g.ensure(sizeof(int32_t) * (size_t)n));
   HIPCHK(W.err.ensure(sizeof(int32_t)));
-  HIPCHK(hipMemcpyAsync(W.tree_off.p, off.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(W.level_cnt.p, lc.data(), sizeof(int32_t) * lc.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(W.root_off.ensure(sizeof(int64_t) * (size_t)n));
+  HIPCHK(W.nroots.ensure(sizeof(int32_t) * (size_t)n));
+  HIPCHK(launch_ingest4(d_states, n, W.inst.as<Inst>(), st));
   HIPCHK(launch_zero_i32(W.err.as<int32_t>(), 1, st));
-  HIPCHK(launch_split4(W.inst.as<Inst>(), n, D, W.tree_off.as<int64_t>(), W.level_cnt.as<int32_t>(),
+  HIPCHK(launch_split4(W.inst.as<Inst>(), n, D, nullptr, stride, W.walks.as<int32_t>(),
                        W.tree.as<Node>(), W.hist.as<uint32_t>(), W.goal_g.as<int32_t>(),
-                       W.err.as<int32_t>(), st));
+                       W.err.as<int32_t>(), W.root_off.as<int64_t>(), W.nroots.as<int32_t>(), st));
 
-  const int per_cu = batch4_max_blocks_per_cu(cap);
-  if (per_cu <= 0) return BPIDA_EDEVICE;
+  const int per_cu = batch4_max_blocks_per_cu(cap, npl);
+  if (per_cu <= 0) return BPIDA_EINVAL;  // unsupported capacity for this round width
   int64_t grid = (int64_t)per_cu * W.num_cu;
   if (O.max_workgroups > 0) grid = std::min<int64_t>(grid, O.max_workgroups);
   uint64_t qcap = 64;
@@ -344,11 +348,6 @@ int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_node
   HIPCHK(W.qseq.ensure(sizeof(uint64_t) * qcap));
   HIPCHK(W.qslots.ensure(sizeof(QChunk) * qcap));
   HIPCHK(W.istate.ensure(sizeof(InstState) * (size_t)n));
-  HIPCHK(W.root_off.ensure(sizeof(int64_t) * (size_t)n));
-  HIPCHK(W.nroots.ensure(sizeof(int32_t) * (size_t)n));
-  HIPCHK(W.status.ensure(sizeof(int32_t) * (size_t)n));
-  HIPCHK(hipMemcpyAsync(W.root_off.p, root_off.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(W.nroots.p, nroots.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st));
   HIPCHK(launch_zero_words(W.qctl.p, sizeof(QueueCtl), st));
 
   BatchArgs A;
@@ -367,10 +366,37 @@ int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_node
   A.idle_ticks = (uint64_t)O.watchdog_ms * (uint64_t)W.wall_khz;
   A.budget_ticks = (uint64_t)O.budget_ms * (uint64_t)W.wall_khz;
   HIPCHK(launch_batch_setup(A, W.inst.as<Inst>(), W.root_off.as<int64_t>(), W.nroots.as<int32_t>(), st));
-  HIPCHK(hipEventRecord(W.ev0, st));
-  HIPCHK(launch_batch4(cap, (int)grid, A, st));
-  HIPCHK(hipEventRecord(W.ev1, st));
-  HIPCHK(launch_batch_status(A.is, n, W.status.as<int32_t>(), st));
+  if (timed) HIPCHK(hipEventRecord(W.ev0, st));
+  HIPCHK(launch_batch4(cap, npl, (int)grid, A, st));
+  if (timed) HIPCHK(hipEventRecord(W.ev1, st));
+  HIPCHK(launch_batch_status(A.is, n, A.q, W.err.as<int32_t>(), d_status, st));
+  *grid_out = grid;
+  return BPIDA_OK;
+#undef HIPCHK
+}
+
+// The batched driver: enqueue, then wait and read the status back.
+int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes, hipStream_t st,
+                const Options& O) {
+  Workspace& W = g_ws;
+  uint64_t stats[16] = {0};
+  hipError_t e;
+#define HIPCHK(x)              \
+  do {                         \
+    e = (x);                   \
+    if (e != hipSuccess) {     \
+      (void)hipGetLastError(); \
+      return map_err(e);       \
+    }                          \
+  } while (0)
+  if (n == 0) {
+    HIPCHK(launch_fill_outputs(d_len, d_nodes, n, st));
+    return BPIDA_OK;
+  }
+  HIPCHK(W.status.ensure(sizeof(int32_t) * (size_t)n));
+  int64_t grid = 0;
+  int rc0 = enqueue_batched(d_states, n, d_len, d_nodes, W.status.as<int32_t>(), st, O, true, &grid);
+  if (rc0 != BPIDA_OK) return rc0;
   std::vector<int32_t> status((size_t)n);
   QueueCtl qc;
   int32_t split_err = 0;
@@ -392,16 +418,9 @@ int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_node
   stats[11] = qc.voluntary;
   stats[12] = (uint64_t)grid;
   memcpy(g_stats, stats, sizeof stats);
-  if (split_err) return BPIDA_EINTERNAL;
-  // a full queue (1, 2, 16) is the root cause of anything that follows it
-  if (qc.err & (1 | 2 | 16)) return BPIDA_ENOMEM;
-  if (qc.err) return BPIDA_EINTERNAL;
   int rc = BPIDA_OK;
-  for (int i = 0; i < n; ++i) {
-    const int s = status[i];
-    if (s != 1 && s != 0 && rc == BPIDA_OK) rc = s;
-    if (s == 0 && rc == BPIDA_OK) rc = BPIDA_EINTERNAL;  // never finished
-  }
+  for (int i = 0; i < n && rc == BPIDA_OK; ++i)
+    if (status[i] != 1) rc = status[i];
   return rc;
 #undef HIPCHK
 }
@@ -467,6 +486,39 @@ extern "C" int bpida_solve_device(const uint8_t* d_states, int32_t n_instances, 
   }
 }
 
+extern "C" int bpida_solve_device_async(const uint8_t* d_states, int32_t n_instances, int32_t width,
+                                        int32_t* d_len, uint64_t* d_nodes, int32_t* d_status,
+                                        void* hip_stream) {
+  try {
+    if (!d_states || !d_len || !d_nodes || !d_status || n_instances < 0) return BPIDA_EINVAL;
+    if (check_opts(width) != BPIDA_OK) return BPIDA_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    const Options O = g_opt;
+    if (n_instances == 0) return BPIDA_OK;
+    int rc = ensure_device();
+    if (rc != BPIDA_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+      (void)hipGetLastError();
+      return BPIDA_EDEVICE;
+    }
+    g_no_alloc = cs != hipStreamCaptureStatusNone;
+    int64_t grid = 0;
+    Options Ob = O;
+    Ob.mode = kModeBatched;
+    rc = enqueue_batched(d_states, n_instances, d_len, d_nodes, d_status, st, Ob, false, &grid);
+    g_no_alloc = false;
+    return rc;
+  } catch (const std::bad_alloc&) {
+    g_no_alloc = false;
+    return BPIDA_ENOMEM;
+  } catch (...) {
+    g_no_alloc = false;
+    return BPIDA_EINTERNAL;
+  }
+}
+
 extern "C" int bpida_set_option(const char* key, int64_t value) {
   if (!key) return BPIDA_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -487,8 +539,12 @@ extern "C" int bpida_set_option(const char* key, int64_t value) {
     if (value < -1 || value > kMaxDepth) return BPIDA_EINVAL;
     g_opt.frontier_depth = value;
   } else if (k == "lds_stack_capacity") {
-    if (value != 128 && value != 256 && value != 512 && value != 1024) return BPIDA_EINVAL;
+    if (value != -1 && value != 128 && value != 256 && value != 512 && value != 1024 && value != 2048)
+      return BPIDA_EINVAL;
     g_opt.lds_stack_capacity = value;
+  } else if (k == "nodes_per_round") {
+    if (value != 16 && value != 64) return BPIDA_EINVAL;
+    g_opt.nodes_per_round = value;
   } else if (k == "spill_capacity") {
     if (value < 64 || value > (1 << 24) || value % 64) return BPIDA_EINVAL;
     g_opt.spill_capacity = value;
@@ -514,6 +570,7 @@ extern "C" int64_t bpida_get_option(const char* key) {
   if (k == "budget_ms") return g_opt.budget_ms;
   if (k == "frontier_depth") return g_opt.frontier_depth;
   if (k == "lds_stack_capacity") return g_opt.lds_stack_capacity;
+  if (k == "nodes_per_round") return g_opt.nodes_per_round;
   if (k == "spill_capacity") return g_opt.spill_capacity;
   if (k == "max_workgroups") return g_opt.max_workgroups;
   if (k == "max_threshold") return g_opt.max_threshold;

@@ -163,15 +163,17 @@ struct BatchArgs {
 
 hipError_t launch_batch_setup(const BatchArgs& A, const Inst* d_inst, const int64_t* d_root_off,
                               const int32_t* d_nroots, hipStream_t s);
-hipError_t launch_batch4(int lds_cap, int grid, const BatchArgs& A, hipStream_t s);
-hipError_t launch_batch_status(const InstState* d_is, int n, int32_t* d_status, hipStream_t s);
-int batch4_max_blocks_per_cu(int lds_cap);
+hipError_t launch_batch4(int lds_cap, int npl, int grid, const BatchArgs& A, hipStream_t s);
+hipError_t launch_batch_status(const InstState* d_is, int n, const QueueCtl* d_q,
+                               const int32_t* d_split_err, int32_t* d_status, hipStream_t s);
+int batch4_max_blocks_per_cu(int lds_cap, int npl);
 
 // Kernel launchers (bpida_kernels.hip).
 hipError_t launch_ingest4(const uint8_t* d_states, int n, Inst* d_inst, hipStream_t s);
 hipError_t launch_split4(const Inst* d_inst, int n, int depth, const int64_t* d_tree_off,
-                         const int32_t* d_level_cnt, Node* d_tree, uint32_t* d_hist,
-                         int32_t* d_goal_g, int32_t* d_err, hipStream_t s);
+                         int64_t stride, const int32_t* d_walks, Node* d_tree, uint32_t* d_hist,
+                         int32_t* d_goal_g, int32_t* d_err, int64_t* d_root_off, int32_t* d_nroots,
+                         hipStream_t s);
 hipError_t launch_search4(int lds_cap, int grid, const Node* d_roots, int nroots, int limit,
                           int32_t* d_cursor, uint64_t* d_spill_tiles, uint16_t* d_spill_meta,
                           int spill_cap, Partial* d_part, hipStream_t s);

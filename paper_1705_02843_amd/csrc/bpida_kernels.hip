@@ -83,17 +83,20 @@ __device__ __forceinline__ int dh_grows(int a, uint32_t t, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// split4: one workgroup of 256 threads per instance.  Level d of the tree
-// occupies tree[off + level_start(d) ...]; the host knows every level's size
-// exactly (the number of non-backtracking blank walks of length d from the
-// start cell) and passes the per-instance level sizes.
+// split4: one workgroup of 256 threads per instance.  Level d of the tree is
+// stored after levels 0..d-1 in the instance's region (tree_off[i], or
+// i * stride when tree_off is null).  Level sizes are exact: walks[c][d] is
+// the number of non-backtracking blank walks of length d from cell c; a
+// level whose fill differs from it raises `err`.  The depth-D level holds
+// the roots; their offset and count go to root_off / nroots when given.
 // ---------------------------------------------------------------------------
 constexpr int kSplitThreads = 256;
 
 __global__ __launch_bounds__(kSplitThreads) void split4_kernel(
-    const Inst* __restrict__ inst, int depth, const int64_t* __restrict__ tree_off,
-    const int32_t* __restrict__ level_cnt, Node* __restrict__ tree, uint32_t* __restrict__ hist,
-    int32_t* __restrict__ goal_g, int32_t* __restrict__ err) {
+    const Inst* __restrict__ inst, int depth, const int64_t* __restrict__ tree_off, int64_t stride,
+    const int32_t* __restrict__ walks, Node* __restrict__ tree, uint32_t* __restrict__ hist,
+    int32_t* __restrict__ goal_g, int32_t* __restrict__ err, int64_t* __restrict__ root_off,
+    int32_t* __restrict__ nroots) {
   const int i = blockIdx.x;
   const Inst I = inst[i];
   __shared__ uint32_t h_lds[kHistBins];
@@ -104,14 +107,19 @@ __global__ __launch_bounds__(kSplitThreads) void split4_kernel(
     gmin = INT_MAX;
     fill = 0;
   }
-  Node* base = tree + tree_off[i];
-  const int32_t* lc = level_cnt + (size_t)i * (kMaxDepth + 1);
+  const int64_t region = tree_off ? tree_off[i] : (int64_t)i * stride;
+  Node* base = tree + region;
   if (I.status != 0) {
     __syncthreads();
     for (int k = threadIdx.x; k < kHistBins; k += kSplitThreads) hist[(size_t)i * kHistBins + k] = 0;
-    if (threadIdx.x == 0) goal_g[i] = INT_MAX;
+    if (threadIdx.x == 0) {
+      goal_g[i] = INT_MAX;
+      if (root_off) root_off[i] = region;
+      if (nroots) nroots[i] = 0;
+    }
     return;
   }
+  const int32_t* lc = walks + (size_t)I.blank * (kMaxDepth + 1);
   if (threadIdx.x == 0) {
     Node r;
     r.tiles = I.tiles;
@@ -152,15 +160,20 @@ __global__ __launch_bounds__(kSplitThreads) void split4_kernel(
     __syncthreads();
   }
   for (int k = threadIdx.x; k < kHistBins; k += kSplitThreads) hist[(size_t)i * kHistBins + k] = h_lds[k];
-  if (threadIdx.x == 0) goal_g[i] = gmin;
+  if (threadIdx.x == 0) {
+    goal_g[i] = gmin;
+    if (root_off) root_off[i] = region + lvl;
+    if (nroots) nroots[i] = lc[depth];
+  }
 }
 
 hipError_t launch_split4(const Inst* d_inst, int n, int depth, const int64_t* d_tree_off,
-                         const int32_t* d_level_cnt, Node* d_tree, uint32_t* d_hist,
-                         int32_t* d_goal_g, int32_t* d_err, hipStream_t s) {
+                         int64_t stride, const int32_t* d_walks, Node* d_tree, uint32_t* d_hist,
+                         int32_t* d_goal_g, int32_t* d_err, int64_t* d_root_off, int32_t* d_nroots,
+                         hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(split4_kernel, dim3(n), dim3(kSplitThreads), 0, s, d_inst, depth, d_tree_off,
-                     d_level_cnt, d_tree, d_hist, d_goal_g, d_err);
+                     stride, d_walks, d_tree, d_hist, d_goal_g, d_err, d_root_off, d_nroots);
   return hipGetLastError();
 }
 
@@ -292,6 +305,9 @@ hipError_t launch_search4(int lds_cap, int grid, const Node* d_roots, int nroots
     case 1024:
       return launch_search4_t<1024>(grid, d_roots, nroots, limit, d_cursor, d_spill_tiles,
                                     d_spill_meta, spill_cap, d_part, s);
+    case 2048:
+      return launch_search4_t<2048>(grid, d_roots, nroots, limit, d_cursor, d_spill_tiles,
+                                    d_spill_meta, spill_cap, d_part, s);
     default:
       return hipErrorInvalidValue;
   }
@@ -305,6 +321,7 @@ int search4_max_blocks_per_cu(int lds_cap) {
     case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, search4_kernel<256>, 64, 0); break;
     case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, search4_kernel<512>, 64, 0); break;
     case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, search4_kernel<1024>, 64, 0); break;
+    case 2048: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, search4_kernel<2048>, 64, 0); break;
     default: break;
   }
   return e == hipSuccess ? nb : 0;

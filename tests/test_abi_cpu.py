@@ -59,7 +59,7 @@ def test_options_roundtrip_and_validation(B):
     B.set_option("frontier_depth", 6)
     assert B.get_option("frontier_depth") == 6
     B.set_option("frontier_depth", old)
-    for k, v in (("frontier_depth", 17), ("frontier_depth", -2), ("lds_stack_capacity", 300), ("mode", 2),
+    for k, v in (("frontier_depth", 17), ("frontier_depth", -2), ("lds_stack_capacity", 300), ("mode", 2), ("nodes_per_round", 32),
                  ("queue_capacity", -1), ("watchdog_ms", 0),
                  ("spill_capacity", 65), ("max_threshold", -2), ("no_such_key", 1)):
         with pytest.raises(B.BpidaError):

@@ -31,8 +31,17 @@ def B():
 
 
 OPTION_KEYS = ("mode", "frontier_depth", "lds_stack_capacity", "spill_capacity",
-               "max_workgroups", "max_threshold", "queue_capacity", "watchdog_ms")
-MODES = {"plain": 0, "batched": 1}
+               "max_workgroups", "max_threshold", "queue_capacity", "watchdog_ms",
+               "nodes_per_round", "budget_ms")
+# plain: one launch per instance and limit, 16-node rounds (Alg. 1's map);
+# batched: persistent launch, 64-node rounds; batched16: persistent, 16-node
+MODES = {"plain": {"mode": 0}, "batched": {"mode": 1, "nodes_per_round": 64},
+         "batched16": {"mode": 1, "nodes_per_round": 16}}
+
+
+def set_mode(B, mode):
+    for k, v in MODES[mode].items():
+        B.set_option(k, v)
 
 
 @pytest.fixture
@@ -74,7 +83,7 @@ def assert_parity(got_len, got_nodes, want_len, want_nodes, tag=""):
 def test_walk40_64_instances_exact(opts, mode):
     B = opts
     _say("case: c1_walk40 full, mode=%s" % mode)
-    B.set_option("mode", MODES[mode])
+    set_mode(B, mode)
     states, want_len, want_nodes = load_golden("c1_walk40")
     rc, ln, nodes = B.solve_raw(states)
     assert rc == B.OK, B.strerror(rc)
@@ -85,7 +94,7 @@ def test_walk40_64_instances_exact(opts, mode):
 def test_md30_38_100_instances_exact(opts, mode):
     B = opts
     _say("case: c2_md30_38 full (100 instances, 2.2e10 nodes), mode=%s" % mode)
-    B.set_option("mode", MODES[mode])
+    set_mode(B, mode)
     states, want_len, want_nodes = load_golden("c2_md30_38")
     rc, ln, nodes = B.solve_raw(states)
     assert rc == B.OK, B.strerror(rc)
@@ -99,7 +108,7 @@ def test_md30_38_100_instances_exact(opts, mode):
 def test_split_depths_agree(opts, depth, mode):
     B = opts
     _say("case: c1 first 24, frontier_depth=%d, mode=%s" % (depth, mode))
-    B.set_option("mode", MODES[mode])
+    set_mode(B, mode)
     states, want_len, want_nodes = load_golden("c1_walk40")
     states, want_len, want_nodes = states[:24], want_len[:24], want_nodes[:24]
     B.set_option("frontier_depth", depth)
@@ -108,12 +117,15 @@ def test_split_depths_agree(opts, depth, mode):
     assert_parity(ln, nodes, want_len, want_nodes, "D=%d" % depth)
 
 
-@pytest.mark.parametrize("mode", sorted(MODES))
-@pytest.mark.parametrize("cap", [128, 256, 1024])
+CAPS = [("plain", 128), ("plain", 1024), ("batched16", 128), ("batched16", 256),
+        ("batched16", 2048), ("batched", 512), ("batched", 1024), ("batched", 2048)]
+
+
+@pytest.mark.parametrize("mode,cap", CAPS)
 def test_lds_capacity_and_spill_agree(opts, cap, mode):
     B = opts
     _say("case: c2 6 instances, lds_stack_capacity=%d, depth 6, mode=%s" % (cap, mode))
-    B.set_option("mode", MODES[mode])
+    set_mode(B, mode)
     states, want_len, want_nodes = load_golden("c2_md30_38")
     pick = [1, 4, 17, 26, 39, 77]
     states, want_len, want_nodes = states[pick], want_len[pick], want_nodes[pick]
@@ -122,7 +134,7 @@ def test_lds_capacity_and_spill_agree(opts, cap, mode):
     rc, ln, nodes = B.solve_raw(states)
     assert rc == B.OK, B.strerror(rc)
     assert_parity(ln, nodes, want_len, want_nodes, "cap=%d" % cap)
-    if cap == 128:
+    if cap == 128 or (mode == "batched" and cap == 512):
         assert B.last_stats()["spilled"] > 0  # the spill path was exercised
 
 
@@ -131,7 +143,7 @@ def test_lds_capacity_and_spill_agree(opts, cap, mode):
 def test_grid_size_does_not_change_counts(opts, maxwg, mode):
     B = opts
     _say("case: c1 first 16, max_workgroups=%d, mode=%s" % (maxwg, mode))
-    B.set_option("mode", MODES[mode])
+    set_mode(B, mode)
     states, want_len, want_nodes = load_golden("c1_walk40")
     states, want_len, want_nodes = states[:16], want_len[:16], want_nodes[:16]
     B.set_option("max_workgroups", maxwg)
@@ -143,7 +155,7 @@ def test_grid_size_does_not_change_counts(opts, maxwg, mode):
 @pytest.mark.parametrize("mode", sorted(MODES))
 def test_short_walks_goal_inside_split_tree(opts, mode):
     B = opts
-    B.set_option("mode", MODES[mode])
+    set_mode(B, mode)
     from paper_1705_02843_amd import instances as I
     _say("case: walks of 0..14 moves, depth 10 (goal inside the split tree)")
     rng = np.random.Generator(np.random.PCG64(77))
@@ -158,7 +170,7 @@ def test_short_walks_goal_inside_split_tree(opts, mode):
 @pytest.mark.parametrize("mode", sorted(MODES))
 def test_invalid_and_unsolvable_mixed_in(opts, mode):
     B = opts
-    B.set_option("mode", MODES[mode])
+    set_mode(B, mode)
     _say("case: batch with invalid and unsolvable states, mode=%s" % mode)
     states, want_len, want_nodes = load_golden("c1_walk40")
     s = states[:5].copy()
@@ -175,7 +187,7 @@ def test_invalid_and_unsolvable_mixed_in(opts, mode):
 @pytest.mark.parametrize("depth", [0, 6])
 def test_goal_and_one_move(opts, mode, depth):
     B = opts
-    B.set_option("mode", MODES[mode])
+    set_mode(B, mode)
     B.set_option("frontier_depth", depth)
     _say("case: goal state and one-move states, mode=%s depth=%d" % (mode, depth))
     g = np.arange(16, dtype=np.uint8)
@@ -190,7 +202,7 @@ def test_goal_and_one_move(opts, mode, depth):
 @pytest.mark.parametrize("mode", sorted(MODES))
 def test_limit_cap_keeps_completed_counts(opts, mode):
     B = opts
-    B.set_option("mode", MODES[mode])
+    set_mode(B, mode)
     _say("case: max_threshold cap, mode=%s" % mode)
     states, want_len, want_nodes = load_golden("c1_walk40")
     s = states[:4]
@@ -211,7 +223,7 @@ def test_limit_cap_keeps_completed_counts(opts, mode):
 def test_device_entry_on_torch_stream(opts, mode):
     import torch
     B = opts
-    B.set_option("mode", MODES[mode])
+    set_mode(B, mode)
     _say("case: bpida_solve_device on a side stream, mode=%s" % mode)
     states, want_len, want_nodes = load_golden("c1_walk40")
     d_states = torch.from_numpy(states).cuda()
@@ -233,6 +245,7 @@ def test_empty_batch(B):
 
 def test_batched_queue_too_small_reports_enomem(opts):
     B = opts
+    set_mode(B, "batched")
     _say("case: batched, one workgroup, 64-chunk queue, 3 instances at depth 12 (~700 seed chunks)")
     B.set_option("mode", 1)
     B.set_option("frontier_depth", 12)
@@ -251,9 +264,19 @@ def test_batched_uneven_batch_exact(opts):
     _say("case: batched, 96 walks of length U{20..120}, max Manhattan 30")
     states, _ = I.walks_uniform_len(96, 4, 20, 120, 30, 31)
     want = oracle_expect(states)
-    B.set_option("mode", 1)
-    rc, ln, nodes = B.solve_raw(states)
-    assert rc == B.OK
-    assert_parity(ln, nodes, want.length, want.nodes, "uneven")
+    for mode in ("batched", "batched16"):
+        set_mode(B, mode)
+        rc, ln, nodes = B.solve_raw(states)
+        assert rc == B.OK
+        assert_parity(ln, nodes, want.length, want.nodes, "uneven " + mode)
     st = B.last_stats()
     _say("stats: %s" % st)
+
+
+def test_batched_rejects_ring_too_small_for_64_node_rounds(opts):
+    B = opts
+    set_mode(B, "batched")
+    B.set_option("lds_stack_capacity", 256)
+    states, _, _ = load_golden("c1_walk40")
+    rc, _, _ = B.solve_raw(states[:2])
+    assert rc == B.EINVAL
