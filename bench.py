@@ -40,6 +40,8 @@ WORKLOADS = {
     "c2_md30_38": ("100 15-puzzle states from seeded 300-move non-backtracking walks, Manhattan "
                    "30..38, all-optimal-solutions final limit", 4),
     "c1_walk40": ("64 15-puzzle states from seeded 40-move non-backtracking walks", 4),
+    "c3_uneven": ("4096 15-puzzle states from seeded non-backtracking walks of length U{20..300}, "
+                  "Manhattan <= 38, all-optimal-solutions final limit", 4),
 }
 MODES = {"plain": 0, "batched": 1}
 
@@ -93,11 +95,11 @@ def cpu_baseline(name, states, budget_nodes, nthreads):
                 len(pick), r.total_nodes, dt, nthreads)}
 
 
-def load_traffic(src_hash, mode):
+def load_traffic(src_hash, mode, workload):
     """Per-launch HBM bytes of the timed search kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "%s_c2_md30_38_traffic.json" % (
-        "batch4" if mode == "batched" else "search4"))
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (
+        "batch4" if mode == "batched" else "search4", workload))
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -120,6 +122,9 @@ def main():
                          "work queue; plain: one launch per instance and f-limit)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip timing the other mode beside it")
+    ap.add_argument("--untuned", action="store_true",
+                    help="ignore the autotuner's table (paper_1705_02843_amd/tuning/) and use the "
+                         "library defaults")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -138,6 +143,12 @@ def main():
     desc, width = WORKLOADS[args.workload]
     states = make_states(args.workload)
     n = states.shape[0]
+    tuned = None
+    if not args.untuned:
+        from paper_1705_02843_amd import autotune
+        tuned = autotune.lookup(n, width)
+        if tuned and args.mode == "batched":
+            autotune.apply(tuned)
     d_states = torch.from_numpy(states).cuda()
     d_len = torch.empty(n, dtype=torch.int32, device="cuda")
     d_nodes = torch.empty((n, bpida.MAX_THRESHOLDS), dtype=torch.int64, device="cuda")
@@ -187,9 +198,13 @@ def main():
     ops_per_launch = search_nodes * OPS_PER_NODE / launches if launches else 0.0
     achieved = ops_per_launch / avg_launch_s / 1e9 if launches else 0.0
     src_hash = kernel_source_hash()
-    traffic = load_traffic(src_hash, args.mode)
+    traffic = load_traffic(src_hash, args.mode, args.workload)
+    npl = bpida.get_option("nodes_per_round") if args.mode == "batched" else 16
     cap = bpida.get_option("lds_stack_capacity")
-    kname = ("batch4_kernel<%d>" if args.mode == "batched" else "search4_kernel<%d>") % cap
+    if cap < 0:
+        cap = 1024 if npl == 64 else 512
+    kname = ("batch4_kernel<%d, %d>" % (cap, npl) if args.mode == "batched"
+             else "search4_kernel<%d>" % cap)
     wg_total = acc.get("wg_us_search", 0) + acc.get("wg_us_queue", 0) + acc.get("wg_us_idle", 0)
 
     out = {
@@ -208,7 +223,10 @@ def main():
         "config": {"workload": args.workload, "description": desc, "n_instances": n,
                    "mode": args.mode,
                    "frontier_depth": bpida.get_option("frontier_depth"),
-                   "lds_stack_capacity": bpida.get_option("lds_stack_capacity")},
+                   "lds_stack_capacity": bpida.get_option("lds_stack_capacity"),
+                   "nodes_per_round": bpida.get_option("nodes_per_round"),
+                   "max_workgroups": bpida.get_option("max_workgroups"),
+                   "tuned": bool(tuned) and args.mode == "batched"},
         "instances_per_s": round(n * args.steps / dt, 2),
         "nodes_per_step": nodes_per_step,
         "roofline": {"bound": "alu", "achieved": round(achieved, 1), "peak": round(PEAK_INT_GOPS, 1),
@@ -229,7 +247,9 @@ def main():
                           "busy_frac": round(acc["wg_us_search"] / wg_total, 4),
                           "queue_frac": round(acc["wg_us_queue"] / wg_total, 4),
                           "chunks_donated_per_step": acc["chunks_pushed"] // max(1, args.steps)}
-    if not args.no_compare:
+    if not args.no_compare and n > 512:
+        out["compare"] = {"skipped": "plain path not timed on batches above 512 states"}
+    elif not args.no_compare:
         other = "plain" if args.mode == "batched" else "batched"
         odt, _, _ = run_mode(other, 1, 1)
         out["compare"] = {"mode": other, "value": round(nodes_per_step / odt, 1),

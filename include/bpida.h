@@ -164,6 +164,9 @@ int64_t bpida_get_option(const char *key);
  *          searching, taking work from the queue, and idle
  *   out[11] batched mode: donations made because workgroups were idle
  *   out[12] batched mode: workgroups in the persistent grid
+ *   out[13] batched mode: error bits (1 queue full while seeding, 2 entries
+ *          dropped, 4 idle watchdog, 8 deadline, 16 queue ring full,
+ *          256 split check)
  * n = number of slots to fill (<= 16).  Returns BPIDA_OK or BPIDA_EINVAL.
  */
 int bpida_last_stats(uint64_t *out, int32_t n);

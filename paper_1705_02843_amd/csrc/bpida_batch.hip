@@ -124,7 +124,9 @@ __device__ bool q_take(const BatchArgs& A, uint64_t& ticket, uint64_t& tile, uin
 // unit so that the limit cannot complete while seeding.  Returns true if the
 // guard's release brought the instance's outstanding count to zero, i.e. the
 // caller must complete the limit itself.
-__device__ bool seed_limit(const BatchArgs& A, int i) {
+// `stage_t` / `stage_m` are 64 entries of LDS the caller does not use while
+// seeding (its stack ring is empty whenever a limit is seeded).
+__device__ bool seed_limit(const BatchArgs& A, int i, uint64_t* stage_t, uint16_t* stage_m) {
   const int lane = threadIdx.x;
   InstState* S = A.is + i;
   const int L = S->limit;
@@ -149,8 +151,8 @@ __device__ bool seed_limit(const BatchArgs& A, int i) {
     const int cnt = __popcll(km);
     if (cnt == 0) continue;
     // compact the kept roots into lanes 0..cnt-1 through LDS
-    __shared__ uint64_t s_t[64];
-    __shared__ uint16_t s_m[64];
+    uint64_t* s_t = stage_t;
+    uint16_t* s_m = stage_m;
     const int off = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
                                               __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
     if (keep) {
@@ -182,7 +184,7 @@ __device__ bool seed_limit(const BatchArgs& A, int i) {
 // Completes the current limit of instance i (its outstanding count is zero
 // and this wave observed it), then advances it.  Loops while a new limit
 // has no queued work.
-__device__ void complete_limit(const BatchArgs& A, int i) {
+__device__ void complete_limit(const BatchArgs& A, int i, uint64_t* stage_t, uint16_t* stage_m) {
   const int lane = threadIdx.x;
   InstState* S = A.is + i;
   for (;;) {
@@ -228,13 +230,14 @@ __device__ void complete_limit(const BatchArgs& A, int i) {
     state = wave_bcast(state);
     if (state != 0) return;
     __syncthreads();
-    if (!seed_limit(A, i)) return;
+    if (!seed_limit(A, i, stage_t, stage_m)) return;
   }
 }
 
 // Adds this workgroup's counts for the unit of instance i it held and
 // releases the unit; completes the limit if it was the last unit.
-__device__ void release_unit(const BatchArgs& A, int i, uint64_t expanded, int goals, int fmin) {
+__device__ void release_unit(const BatchArgs& A, int i, uint64_t expanded, int goals, int fmin,
+                             uint64_t* stage_t, uint16_t* stage_m) {
   const int lane = threadIdx.x;
   InstState* S = A.is + i;
   fmin = wave_min(fmin);
@@ -245,7 +248,7 @@ __device__ void release_unit(const BatchArgs& A, int i, uint64_t expanded, int g
     if (fmin != INT_MAX) __hip_atomic_fetch_min(&S->fmin, fmin, __ATOMIC_RELAXED, AGENT);
     last = __hip_atomic_fetch_add(&S->outstanding, -1, __ATOMIC_ACQ_REL, AGENT) == 1;
   }
-  if (wave_bcast(last)) complete_limit(A, i);
+  if (wave_bcast(last)) complete_limit(A, i, stage_t, stage_m);
 }
 
 // ---------------------------------------------------------------------------
@@ -266,10 +269,16 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
   const LaneMap M = make_lane_map(lane);
   QueueCtl* q = A.q;
 
-  // seed the first limit of this workgroup's share of the instances
-  for (int i = blockIdx.x; i < A.n; i += gridDim.x) {
+  // Seed the first limit of every instance through a shared cursor: all
+  // instances are seeded by workgroups that are running, whatever part of
+  // the grid is resident.
+  for (;;) {
+    int i = 0;
+    if (lane == 0) i = __hip_atomic_fetch_add(&q->seed_next, 1, __ATOMIC_RELAXED, AGENT);
+    i = wave_bcast(i);
+    if (i >= A.n) break;
     if (A.is[i].done != 0) continue;
-    if (seed_limit(A, i)) complete_limit(A, i);
+    if (seed_limit(A, i, st, sm)) complete_limit(A, i, st, sm);
   }
 
   uint64_t rounds = 0, searched = 0, pushes = 0, pops = 0, voluntary = 0;
@@ -299,7 +308,7 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
           const int sm_w = wave_max(smax);
           fmin = sm_w == INT_MIN ? INT_MAX : limit - sm_w;
         }
-        release_unit(A, inst, expanded, goals, fmin);
+        release_unit(A, inst, expanded, goals, fmin, st, sm);
         searched += expanded;
         inst = -1;
       }

@@ -417,6 +417,7 @@ int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_node
   stats[10] = qc.t_idle / (uint64_t)std::max(1, W.wall_khz / 1000);
   stats[11] = qc.voluntary;
   stats[12] = (uint64_t)grid;
+  stats[13] = (uint64_t)(uint32_t)qc.err | ((uint64_t)(split_err != 0) << 8);
   memcpy(g_stats, stats, sizeof stats);
   int rc = BPIDA_OK;
   for (int i = 0; i < n && rc == BPIDA_OK; ++i)

@@ -136,6 +136,7 @@ struct QueueCtl {
   alignas(128) uint64_t head;
   alignas(128) uint64_t tail;
   alignas(128) int32_t remaining;  // instances still searching
+  alignas(128) int32_t seed_next;  // next instance whose first limit is to be seeded
   alignas(128) int32_t err;  // 1: queue full while seeding, 2: entries dropped,
                              // 4: idle watchdog, 8: deadline passed, 16: ring full
   alignas(128) uint64_t rounds;

@@ -27,6 +27,7 @@ SPECS = {
     "c1_walk40": (lambda: instances.c1_walk40(), 4),
     "c2_md30_38": (lambda: instances.c2_md30_38(), 4),
     "c3_uneven_first512": (lambda: tuple(x[:512] for x in instances.c3_uneven()), 4),
+    "c3_uneven": (lambda: instances.c3_uneven(), 4),
 }
 
 

@@ -280,3 +280,30 @@ def test_batched_rejects_ring_too_small_for_64_node_rounds(opts):
     states, _, _ = load_golden("c1_walk40")
     rc, _, _ = B.solve_raw(states[:2])
     assert rc == B.EINVAL
+
+
+def test_c3_4096_batched_exact_where_stored_and_valid_everywhere(opts):
+    """The 4096-state uneven workload in one persistent launch (the grid is
+    smaller than the batch): exact against the stored oracle results, and
+    every instance consistent with its walk and its heuristic."""
+    B = opts
+    from paper_1705_02843_amd import instances as I
+    _say("case: c3_uneven, 4096 states, batched (64-node rounds)")
+    states, walk = I.c3_uneven()
+    set_mode(B, "batched")
+    rc, ln, nodes = B.solve_raw(states)
+    assert rc == B.OK, B.strerror(rc)
+    name = "c3_uneven" if os.path.exists(os.path.join(GOLDEN, "c3_uneven.json")) else \
+        "c3_uneven_first512"
+    gs, want_len, want_nodes = load_golden(name)
+    k = gs.shape[0]
+    assert (gs == states[:k]).all()
+    assert_parity(ln[:k], nodes[:k], want_len, want_nodes, name)
+    h0 = np.array([I.manhattan_filter_value(x, 4) for x in states])
+    assert (ln >= h0).all() and (ln <= walk).all() and ((walk - ln) % 2 == 0).all()
+    ncols = (nodes != 0).sum(axis=1)
+    assert (ncols == (ln - h0) // 2 + 1).all()
+    for i in range(len(states)):
+        row = nodes[i, :ncols[i]]
+        assert (np.diff(row.astype(np.int64)) > 0).all()
+    _say("c3 stats: %s" % B.last_stats())
