@@ -51,7 +51,10 @@ enum bpida_status {
   BPIDA_ENOMEM = -4,      /* device allocation failed, or a per-workgroup spill
                              area overflowed                                    */
   BPIDA_EDEVICE = -5,     /* no usable gfx950 device, or a HIP call failed      */
-  BPIDA_EINTERNAL = -6,   /* a consistency check failed (next limit != L + 2)   */
+  BPIDA_EINTERNAL = -6,   /* a consistency check failed (next limit != L + 2),
+                             or a persistent launch stopped by its watchdog or
+                             time budget                                        */
+  BPIDA_EAGAIN = -7,      /* server: the request ring is full; retry later     */
 };
 
 /*
@@ -104,6 +107,47 @@ int bpida_solve_device(const uint8_t *d_states, int32_t n_instances, int32_t wid
 int bpida_solve_device_async(const uint8_t *d_states, int32_t n_instances, int32_t width,
                              int32_t *d_len, uint64_t *d_nodes, int32_t *d_status,
                              void *hip_stream);
+
+/*
+ * Continuous-batching server (one per process).  bpida_server_start launches
+ * a persistent search kernel on `hip_stream` (NULL: a stream of the
+ * library's own) and returns at once; the kernel keeps running, admitting
+ * requests as they arrive, until bpida_server_stop.  Requests travel through
+ * a ring of `ring_capacity` slots (rounded up to a power of two, >= 64) in
+ * pinned host memory; at most `max_inflight` requests are searched at the
+ * same time (each holds a device slot: split tree, counts, outputs), and a
+ * request that arrives while others are on the GPU is admitted as soon as a
+ * slot frees, its subtrees sharing the work queue with theirs.  Options
+ * (split depth, nodes per round, ring capacity, grid size, budget_ms) are
+ * read at start.  The launch ends when the host has asked to stop and every
+ * admitted request is answered, or after budget_ms.
+ */
+int bpida_server_start(int32_t width, int32_t max_inflight, int32_t ring_capacity,
+                       void *hip_stream);
+
+/*
+ * Queue one start state (host, width*width bytes).  Writes the request's
+ * ticket.  Returns BPIDA_OK, BPIDA_EAGAIN if the ring holds ring_capacity
+ * requests whose results have not been collected yet, or BPIDA_EINVAL.
+ * Invalid or unsolvable states are answered with that status.
+ */
+int bpida_server_submit(const uint8_t *state, uint64_t *ticket);
+
+/*
+ * Collect the answer of `ticket`: returns 1 and fills out_len, out_nodes
+ * (host, BPIDA_MAX_THRESHOLDS uint64 as in bpida_solve) and status (1 solved,
+ * else a negative bpida_status) once it is ready; 0 while it is pending;
+ * BPIDA_EINVAL for an unknown or already collected ticket.  Answers stay
+ * readable after bpida_server_stop until the next bpida_server_start.
+ */
+int bpida_server_poll(uint64_t ticket, int32_t *out_len, uint64_t *out_nodes, int32_t *status);
+
+/*
+ * Ask the server to finish, wait until every admitted request is answered
+ * and the launch has ended.  Returns BPIDA_OK, or the run's error
+ * (BPIDA_ENOMEM: work queue overflow; BPIDA_EINTERNAL: time budget spent).
+ */
+int bpida_server_stop(void);
 
 /*
  * Set a tuning or control option for subsequent calls (process-wide).

@@ -12,13 +12,14 @@ import os
 import numpy as np
 
 MAX_THRESHOLDS = 64
-OK, EINVAL, EUNSOLVABLE, ELIMIT, ENOMEM, EDEVICE, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, EUNSOLVABLE, ELIMIT, ENOMEM, EDEVICE, EINTERNAL, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbpida.so")
 
 EXPORTS = ("bpida_solve", "bpida_solve_device", "bpida_solve_device_async", "bpida_set_option",
-           "bpida_get_option", "bpida_last_stats", "bpida_strerror")
+           "bpida_get_option", "bpida_last_stats", "bpida_strerror", "bpida_server_start",
+           "bpida_server_submit", "bpida_server_poll", "bpida_server_stop")
 
 
 class BpidaError(RuntimeError):
@@ -43,6 +44,16 @@ def _load() -> ctypes.CDLL:
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p]
     lib.bpida_solve_device_async.restype = ctypes.c_int
+    lib.bpida_server_start.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_void_p]
+    lib.bpida_server_start.restype = ctypes.c_int
+    lib.bpida_server_submit.argtypes = [P(ctypes.c_uint8), P(ctypes.c_uint64)]
+    lib.bpida_server_submit.restype = ctypes.c_int
+    lib.bpida_server_poll.argtypes = [ctypes.c_uint64, P(ctypes.c_int32), P(ctypes.c_uint64),
+                                      P(ctypes.c_int32)]
+    lib.bpida_server_poll.restype = ctypes.c_int
+    lib.bpida_server_stop.argtypes = []
+    lib.bpida_server_stop.restype = ctypes.c_int
     lib.bpida_set_option.argtypes = [ctypes.c_char_p, ctypes.c_int64]
     lib.bpida_set_option.restype = ctypes.c_int
     lib.bpida_get_option.argtypes = [ctypes.c_char_p]
@@ -140,3 +151,52 @@ def solve_device_async(d_states, d_len, d_nodes, d_status, width: int = 4, strea
                                             ctypes.c_void_p(d_nodes.data_ptr()),
                                             ctypes.c_void_p(d_status.data_ptr()),
                                             ctypes.c_void_p(s.cuda_stream)))
+
+
+class Server:
+    """Continuous-batching server on the C ABI (one per process)."""
+
+    def __init__(self, max_inflight: int = 512, ring_capacity: int = 4096, width: int = 4):
+        self.width = width
+        rc = lib.bpida_server_start(width, max_inflight, ring_capacity, None)
+        if rc != OK:
+            raise BpidaError(rc, "bpida_server_start")
+        self.running = True
+
+    def submit(self, state) -> int | None:
+        """Queue one state; returns its ticket, or None if the ring is full."""
+        st = np.ascontiguousarray(np.asarray(state, dtype=np.uint8).reshape(-1))
+        t = ctypes.c_uint64(0)
+        rc = lib.bpida_server_submit(st.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                     ctypes.byref(t))
+        if rc == EAGAIN:
+            return None
+        if rc != OK:
+            raise BpidaError(rc, "bpida_server_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """(length, nodes uint64[64], status) once answered, else None."""
+        ln = ctypes.c_int32(0)
+        stt = ctypes.c_int32(0)
+        nodes = np.zeros(MAX_THRESHOLDS, np.uint64)
+        rc = lib.bpida_server_poll(ticket, ctypes.byref(ln),
+                                   nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                   ctypes.byref(stt))
+        if rc == 0:
+            return None
+        if rc != 1:
+            raise BpidaError(rc, "bpida_server_poll")
+        return int(ln.value), nodes, int(stt.value)
+
+    def stop(self) -> int:
+        if not self.running:
+            return OK
+        self.running = False
+        return int(lib.bpida_server_stop())
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()

@@ -181,6 +181,27 @@ __device__ bool seed_limit(const BatchArgs& A, int i, uint64_t* stage_t, uint16_
   return wave_bcast(last) != 0;
 }
 
+// Server mode: copy slot i's answer into the pinned result ring, publish it,
+// and free the slot.  Executed by one wave after the slot's outputs are final.
+__device__ void emit_result(const BatchArgs& A, int i, int status) {
+  const int lane = threadIdx.x;
+  const ServerArgs& V = A.srv;
+  __syncthreads();  // the slot's output row, written by lane 0, is visible
+  const uint64_t t = V.ticket[i];
+  ServerRes* r = V.res + (t & V.ring_mask);
+  r->nodes[lane] = A.out_nodes[(size_t)i * 64 + lane];
+  if (lane == 0) {
+    r->len = A.out_len[i];
+    r->status = status;
+  }
+  __syncthreads();
+  if (lane == 0) {
+    __hip_atomic_store(&r->seq, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&V.busy[i], 0, __ATOMIC_RELEASE, AGENT);
+    __hip_atomic_fetch_add(V.in_flight, -1, __ATOMIC_RELEASE, AGENT);
+  }
+}
+
 // Completes the current limit of instance i (its outstanding count is zero
 // and this wave observed it), then advances it.  Loops while a new limit
 // has no queued work.
@@ -218,7 +239,7 @@ __device__ void complete_limit(const BatchArgs& A, int i, uint64_t* stage_t, uin
       }
       if (state != 0) {
         __hip_atomic_store(&S->done, state, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_fetch_add(&A.q->remaining, -1, __ATOMIC_RELEASE, AGENT);
+        if (!A.server) __hip_atomic_fetch_add(&A.q->remaining, -1, __ATOMIC_RELEASE, AGENT);
       } else {
         S->limit = L + 2;
         S->col = col + 1;
@@ -228,9 +249,213 @@ __device__ void complete_limit(const BatchArgs& A, int i, uint64_t* stage_t, uin
       }
     }
     state = wave_bcast(state);
-    if (state != 0) return;
+    if (state != 0) {
+      if (A.server) emit_result(A, i, state);
+      return;
+    }
     __syncthreads();
     if (!seed_limit(A, i, stage_t, stage_m)) return;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Server admission, executed by the one workgroup holding the admitter role.
+// ---------------------------------------------------------------------------
+
+// Validate and pack a state of 16 bytes (in pinned host memory) with one wave.
+__device__ Inst wave_ingest4(const uint8_t* src) {
+  const int lane = threadIdx.x;
+  const uint32_t v = lane < 16 ? (uint32_t)src[lane] : 0u;
+  // permutation: every value 0..15 exactly once
+  uint32_t seen = lane < 16 && v < 16 ? (1u << v) : 0u;
+  for (int o = 32; o > 0; o >>= 1) seen |= __shfl_xor(seen, o, 64);
+  const uint64_t valid = __builtin_amdgcn_ballot_w64(lane < 16 && v < 16);
+  const uint64_t blank_m = __builtin_amdgcn_ballot_w64(lane < 16 && v == 0);
+  // inversions: lane p counts q > p with v[q] < v[p]
+  uint32_t inv = 0;
+  for (int q = 0; q < 16; ++q) {
+    const uint32_t vq = (uint32_t)__shfl((int)v, q, 64);
+    inv += (lane < 16 && q > lane && vq < v) ? 1u : 0u;
+  }
+  int h = 0;
+  if (lane < 16 && v != 0) {
+    const int dr = (lane >> 2) - (int)(v >> 2), dc = (lane & 3) - (int)(v & 3);
+    h = (dr < 0 ? -dr : dr) + (dc < 0 ? -dc : dc);
+  }
+  uint64_t word = lane < 16 ? (uint64_t)(v & 15u) << (4 * lane) : 0ull;
+  for (int o = 32; o > 0; o >>= 1) {
+    inv += (uint32_t)__shfl_xor((int)inv, o, 64);
+    h += __shfl_xor(h, o, 64);
+    word |= (uint64_t)__shfl_xor((long long)word, o, 64);
+  }
+  Inst I;
+  I.tiles = word;
+  I.blank = blank_m ? (int)__builtin_ctzll(blank_m) : 0;
+  I.h0 = h;
+  I.pad = 0;
+  if (seen != 0xFFFFu || valid != 0xFFFFull) I.status = -1;  // BPIDA_EINVAL
+  else {
+    const uint32_t bpar = (uint32_t)((I.blank >> 2) + (I.blank & 3)) & 1u;
+    I.status = ((inv & 1u) == bpar) ? 0 : -2;  // BPIDA_EUNSOLVABLE
+  }
+  return I;
+}
+
+// The root split of one instance with one wave (CreateRootSet; same tree as
+// split4_kernel): levels 0..depth of the parent-pruned tree are written to
+// base[], interior nodes binned by f in hist_lds (256 entries of LDS).
+// Returns the first root's index inside base; the root count is
+// walks[blank][depth].
+__device__ int64_t wave_split4(const Inst& I, int depth, const int32_t* walks, Node* base,
+                               uint32_t* hist_lds, uint32_t* hist_out, int32_t* goal_g_out) {
+  const int lane = threadIdx.x;
+  for (int k = lane; k < kHistBins; k += 64) hist_lds[k] = 0;
+  if (lane == 0) {
+    Node r;
+    r.tiles = I.tiles;
+    r.meta = node_meta(I.blank, 4, 0, I.h0);
+    r.f = (uint32_t)I.h0;
+    base[0] = r;
+  }
+  __syncthreads();
+  const int32_t* lc = walks + (size_t)I.blank * (kMaxDepth + 1);
+  int gmin = INT_MAX;
+  int64_t lvl = 0;
+  for (int d = 0; d < depth; ++d) {
+    const int cnt = lc[d];
+    const int64_t next = lvl + cnt;
+    int64_t fill = next;
+    for (int k0 = 0; k0 < cnt; k0 += 64) {
+      const int k = k0 + lane;
+      Node nd;
+      nd.tiles = 0;
+      nd.meta = 0;
+      nd.f = 0;
+      if (k < cnt) nd = base[lvl + k];
+      const int b = (int)(nd.meta & 15u), fb = (int)((nd.meta >> 4) & 7u);
+      const int g = (int)((nd.meta >> 8) & 255u), h = (int)((nd.meta >> 16) & 255u);
+      if (k < cnt) {
+        atomicAdd(&hist_lds[min(g + h, kHistBins - 1)], 1u);
+        if (nd.tiles == kGoal4) gmin = min(gmin, g);
+      }
+      for (int a = 0; a < 4; ++a) {
+        const bool ok = k < cnt && ((kMoveMask4 >> (4 * b + a)) & 1ull) && a != fb;
+        const int nn = (b + (a == 0 ? -4 : a == 1 ? -1 : a == 2 ? 1 : 4)) & 15;
+        const uint32_t t = (uint32_t)(nd.tiles >> (4 * nn)) & 15u;
+        const int sh = (a == 0 || a == 3) ? 2 : 0;
+        const uint32_t idx = (((t >> sh) & 3u) << 2) | (((uint32_t)nn >> sh) & 3u);
+        const int h2 = h + (((kDhTable4 >> (16 * a + idx)) & 1ull) ? 1 : -1);
+        const uint64_t km = __builtin_amdgcn_ballot_w64(ok);
+        const int off = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+        if (ok && fill + off < next + lc[d + 1]) {  // the level's exact size bounds it
+          Node c;
+          c.tiles = nd.tiles + ((uint64_t)t << (4 * b)) - ((uint64_t)t << (4 * nn));
+          c.meta = node_meta(nn, 3 - a, g + 1, h2);
+          c.f = (uint32_t)(g + 1 + h2);
+          base[fill + off] = c;
+        }
+        fill += __popcll(km);
+      }
+    }
+    __syncthreads();  // this level's children are visible to the whole wave
+    lvl = next;
+  }
+  gmin = wave_min(gmin);
+  for (int k = lane; k < kHistBins; k += 64) hist_out[k] = hist_lds[k];
+  if (lane == 0) *goal_g_out = gmin;
+  __syncthreads();
+  return lvl;
+}
+
+// Admits requests until the host asks to stop and nothing is in flight.
+__device__ void admitter_loop(const BatchArgs& A, uint64_t* st, uint16_t* sm, uint64_t deadline) {
+  const int lane = threadIdx.x;
+  const ServerArgs& V = A.srv;
+  QueueCtl* q = A.q;
+  uint32_t* hist_lds = (uint32_t*)st;  // the ring is unused by the admitter
+  uint64_t head = 0;
+  int cursor = 0;
+  for (;;) {
+    if (wall_clock64() > deadline) {
+      if (lane == 0) {
+        atomicOr(&q->err, 8);
+        __hip_atomic_store(&q->remaining, 0, __ATOMIC_RELEASE, AGENT);
+      }
+      return;
+    }
+    uint64_t tail = 0;
+    int stop = 0, busy_all = 0;
+    if (lane == 0) {
+      tail = __hip_atomic_load(&V.host->req_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+      stop = __hip_atomic_load(&V.host->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    tail = bcast64(tail);
+    stop = wave_bcast(stop);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // request bytes published before req_tail
+    if (tail == head) {
+      if (stop) {
+        int inflight = 0;
+        if (lane == 0) inflight = __hip_atomic_load(V.in_flight, __ATOMIC_ACQUIRE, AGENT);
+        if (wave_bcast(inflight) == 0) {
+          if (lane == 0) __hip_atomic_store(&q->remaining, 0, __ATOMIC_RELEASE, AGENT);
+          return;
+        }
+      }
+      __builtin_amdgcn_s_sleep(32);
+      continue;
+    }
+    // a free instance slot (the in-flight budget); wait if none
+    int slot = -1;
+    for (int k0 = 0; k0 < V.slots && slot < 0; k0 += 64) {
+      const int j = (cursor + k0 + lane) % V.slots;
+      const bool fr = k0 + lane < V.slots &&
+                      __hip_atomic_load(&V.busy[j], __ATOMIC_ACQUIRE, AGENT) == 0;
+      const uint64_t fm = __builtin_amdgcn_ballot_w64(fr);
+      if (fm) slot = (cursor + k0 + (int)__builtin_ctzll(fm)) % V.slots;
+    }
+    if (slot < 0) {
+      busy_all = 1;
+      __builtin_amdgcn_s_sleep(32);
+      continue;
+    }
+    (void)busy_all;
+    cursor = (slot + 1) % V.slots;
+    const Inst I = wave_ingest4(V.req[head & V.ring_mask].state);
+    if (lane == 0) {
+      __hip_atomic_store(&V.host->req_admitted, head + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      V.busy[slot] = 1;
+      V.ticket[slot] = head;
+      __hip_atomic_fetch_add(V.in_flight, 1, __ATOMIC_RELAXED, AGENT);
+    }
+    A.out_nodes[(size_t)slot * 64 + lane] = 0;
+    if (lane == 0) A.out_len[slot] = -1;
+    InstState S;
+    S.limit = I.h0;
+    S.col = 0;
+    S.done = I.status;
+    S.outstanding = 0;
+    S.nodes = 0;
+    S.fmin = INT_MAX;
+    S.goals = 0;
+    S.root_off = (int64_t)slot * V.stride;
+    S.nroots = 0;
+    S.pad = 0;
+    if (I.status == 0) {
+      Node* base = const_cast<Node*>(A.tree) + (int64_t)slot * V.stride;
+      const int64_t r0 = wave_split4(I, V.depth, V.walks, base, hist_lds,
+                                     const_cast<uint32_t*>(A.hist) + (size_t)slot * kHistBins,
+                                     const_cast<int32_t*>(A.goal_g) + slot);
+      S.root_off += r0;
+      S.nroots = V.walks[(size_t)I.blank * (kMaxDepth + 1) + V.depth];
+      if (S.limit > A.max_limit) S.done = -3;  // BPIDA_ELIMIT
+    }
+    if (lane == 0) A.is[slot] = S;
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (S.done != 0) emit_result(A, slot, S.done);
+    else if (seed_limit(A, slot, st, sm)) complete_limit(A, slot, st, sm);
+    ++head;
   }
 }
 
@@ -268,6 +493,15 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
   const int lane = threadIdx.x;
   const LaneMap M = make_lane_map(lane);
   QueueCtl* q = A.q;
+
+  if (A.server) {
+    int role = 0;
+    if (lane == 0) role = atomicCAS(A.srv.admitter, 0, 1) == 0;
+    if (wave_bcast(role)) {
+      admitter_loop(A, st, sm, wall_clock64() + A.budget_ticks);
+      return;
+    }
+  }
 
   // Seed the first limit of every instance through a shared cursor: all
   // instances are seeded by workgroups that are running, whatever part of
@@ -488,6 +722,25 @@ __global__ void batch_status_kernel(const InstState* __restrict__ is, int n,
   else if (q->err & (1 | 2 | 16)) v = -4;   // BPIDA_ENOMEM
   else if (done == 0) v = -6;               // stopped by the watchdog or the deadline
   st[k] = v;
+}
+
+// Server set-up: queue sequence numbers, free instance slots, one sentinel in
+// `remaining` (cleared by the admitter when the server shuts down).
+__global__ void server_setup_kernel(BatchArgs A) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k <= (int64_t)A.qmask) A.seq[k] = (uint64_t)k;
+  if (k < A.srv.slots) A.srv.busy[k] = 0;
+  if (k == 0) {
+    A.q->remaining = 1;
+    *A.srv.admitter = 0;
+    *A.srv.in_flight = 0;
+  }
+}
+
+hipError_t launch_server_setup(const BatchArgs& A, hipStream_t s) {
+  const int64_t work = std::max<int64_t>((int64_t)A.qmask + 1, A.srv.slots);
+  hipLaunchKernelGGL(server_setup_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, A);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch_setup(const BatchArgs& A, const Inst* d_inst, const int64_t* d_root_off,

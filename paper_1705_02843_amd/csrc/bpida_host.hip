@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <string>
@@ -362,6 +363,8 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
   A.out_len = d_len;
   A.out_nodes = d_nodes;
   A.n = n;
+  A.server = 0;
+  memset(&A.srv, 0, sizeof A.srv);
   A.max_limit = (int)(O.max_threshold >= 0 ? std::min<int64_t>(O.max_threshold, kMaxLimit) : kMaxLimit);
   A.idle_ticks = (uint64_t)O.watchdog_ms * (uint64_t)W.wall_khz;
   A.budget_ticks = (uint64_t)O.budget_ms * (uint64_t)W.wall_khz;
@@ -487,6 +490,225 @@ extern "C" int bpida_solve_device(const uint8_t* d_states, int32_t n_instances, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Continuous-batching server.
+// ---------------------------------------------------------------------------
+namespace bpida {
+namespace {
+
+struct Server {
+  bool running = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  uint64_t ring = 0;
+  ServerHostCtl* host = nullptr;
+  ServerReq* req = nullptr;
+  ServerRes* res = nullptr;
+  std::vector<uint8_t> collected;
+  uint64_t tail = 0, min_uncollected = 0;
+  DevBuf qctl, qseq, qslots, istate, tree, hist, goal_g, out_len, out_nodes, busy, ticket, admitter,
+      inflight;
+  int64_t grid = 0;
+};
+
+Server g_srv;
+
+void free_server_host(Server& V) {
+  if (V.host) (void)hipHostFree(V.host);
+  if (V.req) (void)hipHostFree(V.req);
+  if (V.res) (void)hipHostFree(V.res);
+  V.host = nullptr;
+  V.req = nullptr;
+  V.res = nullptr;
+}
+
+}  // namespace
+}  // namespace bpida
+
+extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t ring_capacity,
+                                  void* hip_stream) {
+  try {
+    if (check_opts(width) != BPIDA_OK || max_inflight < 1 || max_inflight > (1 << 16) ||
+        ring_capacity < 1 || ring_capacity > (1 << 20))
+      return BPIDA_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Server& V = g_srv;
+    if (V.running) return BPIDA_EINVAL;
+    int rc = ensure_device();
+    if (rc != BPIDA_OK) return rc;
+    Workspace& W = g_ws;
+    Options O = g_opt;
+    O.mode = kModeBatched;
+    const int D = depth_for(O);
+    const int npl = (int)O.nodes_per_round;
+    const int cap = cap_for(O, npl);
+    const int per_cu = batch4_max_blocks_per_cu(cap, npl);
+    if (per_cu <= 0) return BPIDA_EINVAL;
+    int64_t grid = (int64_t)per_cu * W.num_cu;
+    if (O.max_workgroups > 0) grid = std::min<int64_t>(grid, O.max_workgroups);
+    if (grid < 2) return BPIDA_EINVAL;  // one admitter plus at least one searcher
+    int64_t stride = 0, max_roots = 0;
+    for (int c = 0; c < 16; ++c) {
+      int64_t tot = 0;
+      for (int d = 0; d <= D; ++d) tot += W.h_walks[c][d];
+      stride = std::max(stride, tot);
+      max_roots = std::max<int64_t>(max_roots, W.h_walks[c][D]);
+    }
+    const int64_t S = max_inflight;
+    uint64_t ring = 64;
+    while (ring < (uint64_t)ring_capacity) ring <<= 1;
+    uint64_t qcap = 64;
+    const uint64_t want = O.queue_capacity > 0
+                              ? (uint64_t)O.queue_capacity
+                              : (uint64_t)(S * ((max_roots + kQChunk - 1) / kQChunk) + grid * 16 + 1024);
+    while (qcap < want) qcap <<= 1;
+    free_server_host(V);
+    if (V.qctl.ensure(sizeof(QueueCtl)) != hipSuccess || V.qseq.ensure(sizeof(uint64_t) * qcap) != hipSuccess ||
+        V.qslots.ensure(sizeof(QChunk) * qcap) != hipSuccess ||
+        V.istate.ensure(sizeof(InstState) * S) != hipSuccess ||
+        V.tree.ensure(sizeof(Node) * S * stride) != hipSuccess ||
+        V.hist.ensure(sizeof(uint32_t) * kHistBins * S) != hipSuccess ||
+        V.goal_g.ensure(sizeof(int32_t) * S) != hipSuccess ||
+        V.out_len.ensure(sizeof(int32_t) * S) != hipSuccess ||
+        V.out_nodes.ensure(sizeof(uint64_t) * 64 * S) != hipSuccess ||
+        V.busy.ensure(sizeof(int32_t) * S) != hipSuccess ||
+        V.ticket.ensure(sizeof(uint64_t) * S) != hipSuccess ||
+        V.admitter.ensure(sizeof(int32_t)) != hipSuccess || V.inflight.ensure(sizeof(int32_t)) != hipSuccess)
+      return BPIDA_ENOMEM;
+    const unsigned fl = hipHostMallocCoherent | hipHostMallocMapped;
+    if (hipHostMalloc((void**)&V.host, sizeof(ServerHostCtl), fl) != hipSuccess ||
+        hipHostMalloc((void**)&V.req, sizeof(ServerReq) * ring, fl) != hipSuccess ||
+        hipHostMalloc((void**)&V.res, sizeof(ServerRes) * ring, fl) != hipSuccess) {
+      (void)hipGetLastError();
+      free_server_host(V);
+      return BPIDA_ENOMEM;
+    }
+    memset((void*)V.host, 0, sizeof(ServerHostCtl));
+    memset((void*)V.req, 0, sizeof(ServerReq) * ring);
+    memset((void*)V.res, 0, sizeof(ServerRes) * ring);
+    V.ring = ring;
+    V.collected.assign(ring, 0);
+    V.tail = 0;
+    V.min_uncollected = 0;
+    V.grid = grid;
+    if (hip_stream) {
+      V.stream = (hipStream_t)hip_stream;
+      V.own_stream = false;
+    } else if (!V.stream || !V.own_stream) {
+      if (hipStreamCreateWithFlags(&V.stream, hipStreamNonBlocking) != hipSuccess) return BPIDA_EDEVICE;
+      V.own_stream = true;
+    }
+    BatchArgs A;
+    memset(&A, 0, sizeof A);
+    A.q = V.qctl.as<QueueCtl>();
+    A.seq = V.qseq.as<uint64_t>();
+    A.slots = V.qslots.as<QChunk>();
+    A.qmask = qcap - 1;
+    A.is = V.istate.as<InstState>();
+    A.tree = V.tree.as<Node>();
+    A.hist = V.hist.as<uint32_t>();
+    A.goal_g = V.goal_g.as<int32_t>();
+    A.out_len = V.out_len.as<int32_t>();
+    A.out_nodes = V.out_nodes.as<uint64_t>();
+    A.n = 0;
+    A.max_limit = (int)(O.max_threshold >= 0 ? std::min<int64_t>(O.max_threshold, kMaxLimit) : kMaxLimit);
+    A.idle_ticks = ~0ull;  // waiting for requests is not a stall
+    A.budget_ticks = (uint64_t)O.budget_ms * (uint64_t)W.wall_khz;
+    A.server = 1;
+    A.srv.host = V.host;
+    A.srv.req = V.req;
+    A.srv.res = V.res;
+    A.srv.ring_mask = ring - 1;
+    A.srv.slots = (int32_t)S;
+    A.srv.depth = D;
+    A.srv.stride = stride;
+    A.srv.busy = V.busy.as<int32_t>();
+    A.srv.ticket = V.ticket.as<uint64_t>();
+    A.srv.walks = W.walks.as<int32_t>();
+    A.srv.admitter = V.admitter.as<int32_t>();
+    A.srv.in_flight = V.inflight.as<int32_t>();
+    if (launch_zero_words(V.qctl.p, sizeof(QueueCtl), V.stream) != hipSuccess ||
+        launch_server_setup(A, V.stream) != hipSuccess ||
+        launch_batch4(cap, npl, (int)grid, A, V.stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return BPIDA_EDEVICE;
+    }
+    V.running = true;
+    return BPIDA_OK;
+  } catch (const std::bad_alloc&) {
+    return BPIDA_ENOMEM;
+  } catch (...) {
+    return BPIDA_EINTERNAL;
+  }
+}
+
+extern "C" int bpida_server_submit(const uint8_t* state, uint64_t* ticket) {
+  if (!state || !ticket) return BPIDA_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Server& V = g_srv;
+  if (!V.running) return BPIDA_EINVAL;
+  const uint64_t admitted = __atomic_load_n(&V.host->req_admitted, __ATOMIC_ACQUIRE);
+  if (V.tail - V.min_uncollected >= V.ring || V.tail - admitted >= V.ring) return BPIDA_EAGAIN;
+  memcpy(V.req[V.tail & (V.ring - 1)].state, state, 16);
+  std::atomic_thread_fence(std::memory_order_release);
+  __atomic_store_n(&V.host->req_tail, V.tail + 1, __ATOMIC_RELEASE);
+  *ticket = V.tail++;
+  return BPIDA_OK;
+}
+
+extern "C" int bpida_server_poll(uint64_t ticket, int32_t* out_len, uint64_t* out_nodes,
+                                 int32_t* status) {
+  if (!out_len || !out_nodes || !status) return BPIDA_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Server& V = g_srv;
+  if (!V.res || ticket >= V.tail || ticket < V.min_uncollected || V.collected[ticket & (V.ring - 1)])
+    return BPIDA_EINVAL;
+  const ServerRes* r = V.res + (ticket & (V.ring - 1));
+  if (__atomic_load_n(&r->seq, __ATOMIC_ACQUIRE) != ticket + 1) return 0;
+  *out_len = r->len;
+  *status = r->status;
+  memcpy(out_nodes, (const void*)r->nodes, sizeof(uint64_t) * 64);
+  V.collected[ticket & (V.ring - 1)] = 1;
+  while (V.min_uncollected < V.tail && V.collected[V.min_uncollected & (V.ring - 1)]) {
+    V.collected[V.min_uncollected & (V.ring - 1)] = 0;
+    ++V.min_uncollected;
+  }
+  return 1;
+}
+
+extern "C" int bpida_server_stop(void) {
+  try {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Server& V = g_srv;
+    if (!V.running) return BPIDA_EINVAL;
+    __atomic_store_n(&V.host->stop, 1, __ATOMIC_RELEASE);
+    QueueCtl qc;
+    if (hipStreamSynchronize(V.stream) != hipSuccess ||
+        hipMemcpy(&qc, V.qctl.p, sizeof(QueueCtl), hipMemcpyDeviceToHost) != hipSuccess) {
+      (void)hipGetLastError();
+      V.running = false;
+      return BPIDA_EDEVICE;
+    }
+    V.running = false;
+    uint64_t stats[16] = {0};
+    stats[0] = qc.rounds;
+    stats[1] = qc.searched;
+    stats[2] = qc.pushes * kQChunk;
+    stats[3] = 1;
+    stats[6] = qc.pushes;
+    stats[7] = qc.pops;
+    stats[11] = qc.voluntary;
+    stats[12] = (uint64_t)V.grid;
+    stats[13] = (uint64_t)(uint32_t)qc.err;
+    memcpy(g_stats, stats, sizeof stats);
+    if (qc.err & (1 | 2 | 16)) return BPIDA_ENOMEM;
+    if (qc.err) return BPIDA_EINTERNAL;
+    return BPIDA_OK;
+  } catch (...) {
+    return BPIDA_EINTERNAL;
+  }
+}
+
 extern "C" int bpida_solve_device_async(const uint8_t* d_states, int32_t n_instances, int32_t width,
                                         int32_t* d_len, uint64_t* d_nodes, int32_t* d_status,
                                         void* hip_stream) {
@@ -594,6 +816,7 @@ extern "C" const char* bpida_strerror(int code) {
     case BPIDA_ENOMEM: return "out of device memory or spill area";
     case BPIDA_EDEVICE: return "no usable gfx950 device or HIP failure";
     case BPIDA_EINTERNAL: return "internal consistency check failed";
+    case BPIDA_EAGAIN: return "server request ring full, try again";
     default: return "unknown status";
   }
 }

@@ -145,6 +145,44 @@ struct QueueCtl {
   uint64_t voluntary;                // donations made because workgroups idled
 };
 
+// ---------------------------------------------------------------------------
+// Continuous-batching server: requests arrive through a ring in pinned host
+// memory while the persistent kernel runs; each is admitted into a free
+// instance slot (the device-memory budget), searched alongside the others
+// and answered through a result ring in pinned host memory.
+// ---------------------------------------------------------------------------
+struct ServerReq {
+  uint8_t state[16];
+};
+
+struct ServerRes {
+  uint64_t seq;     // ticket + 1 once the fields below are final
+  int32_t len;      // optimal length or -1
+  int32_t status;   // 1 solved, < 0 bpida_status
+  uint64_t nodes[64];
+};
+
+struct ServerHostCtl {
+  alignas(128) uint64_t req_tail;      // requests published (host writes)
+  alignas(128) int32_t stop;           // host asks the server to finish
+  alignas(128) uint64_t req_admitted;  // requests copied to the device (device writes)
+};
+
+struct ServerArgs {
+  ServerHostCtl* host;  // pinned host memory
+  const ServerReq* req; // pinned ring of requests
+  ServerRes* res;       // pinned ring of results
+  uint64_t ring_mask;   // ring capacity - 1
+  int32_t slots;        // instance slots (in-flight budget)
+  int32_t depth;        // root split depth
+  int64_t stride;       // split-tree nodes per slot
+  int32_t* busy;        // per slot: 1 while a request occupies it
+  uint64_t* ticket;     // per slot: request ticket
+  const int32_t* walks; // walk counts per start cell and length
+  int32_t* admitter;    // 0 until a workgroup takes the admitter role
+  int32_t* in_flight;   // admitted, not yet answered
+};
+
 struct BatchArgs {
   QueueCtl* q;
   uint64_t* seq;       // per slot sequence number
@@ -160,7 +198,11 @@ struct BatchArgs {
   int32_t max_limit;
   uint64_t idle_ticks;   // an idle workgroup gives up after this many wall-clock ticks
   uint64_t budget_ticks; // every workgroup stops this many ticks after it starts
+  int32_t server;        // nonzero: continuous-batching server (srv below)
+  ServerArgs srv;
 };
+
+hipError_t launch_server_setup(const BatchArgs& A, hipStream_t s);
 
 hipError_t launch_batch_setup(const BatchArgs& A, const Inst* d_inst, const int64_t* d_root_off,
                               const int32_t* d_nroots, hipStream_t s);

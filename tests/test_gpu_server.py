@@ -1,0 +1,130 @@
+"""Continuous batching: requests submitted while others are being searched.
+
+Every answer must equal the oracle's result for that state alone (exact
+integers: length and every per-limit node count), whatever else was in
+flight; invalid requests get their status; a full request ring reports
+EAGAIN and recovers once answers are collected.
+"""
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def load_golden(name):
+    g = json.load(open(os.path.join(GOLDEN, name + ".json")))
+    states = np.array([[int(c, 16) for c in rec["state"]] for rec in g["instances"]], np.uint8)
+    length = np.array([rec["length"] for rec in g["instances"]], np.int32)
+    nodes = np.zeros((len(g["instances"]), 64), np.uint64)
+    for i, rec in enumerate(g["instances"]):
+        nodes[i, :len(rec["nodes"])] = rec["nodes"]
+    return states, length, nodes
+
+
+@pytest.fixture
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1705_02843_amd import bpida
+    saved = {k: bpida.get_option(k) for k in ("budget_ms", "frontier_depth")}
+    bpida.set_option("budget_ms", 90000)
+    yield bpida
+    for k, v in saved.items():
+        bpida.set_option(k, v)
+
+
+def drain(srv, pending, got, deadline):
+    while pending and time.time() < deadline:
+        for t in list(pending):
+            r = srv.poll(t)
+            if r is not None:
+                got[pending.pop(t)] = r
+        time.sleep(0.0005)
+
+
+def test_mixed_stream_answers_equal_alone_results(B):
+    print("case: server, 64 + 24 golden states and 2 bad ones, random gaps", flush=True)
+    s1, l1, n1 = load_golden("c1_walk40")
+    s2, l2, n2 = load_golden("c2_md30_38")
+    pick = [0, 3, 7, 12, 18, 25, 31, 44, 50, 63, 66, 70, 75, 80, 88, 91, 95, 99, 5, 9, 14, 21,
+            40, 57]
+    states = np.concatenate([s1, s2[pick]])
+    want_len = np.concatenate([l1, l2[pick]])
+    want_nodes = np.concatenate([n1, n2[pick]])
+    bad_perm = s1[0].copy()
+    bad_perm[1], bad_perm[2] = bad_perm[2], bad_perm[1]
+    bad_dup = s1[1].copy()
+    bad_dup[0] = bad_dup[3]
+    rng = np.random.default_rng(0)
+    order = rng.permutation(len(states))
+    got, pending = {}, {}
+    with B.Server(max_inflight=64, ring_capacity=256) as srv:
+        t_bad1 = srv.submit(bad_perm)
+        for k in order:
+            t = srv.submit(states[k])
+            assert t is not None
+            pending[t] = int(k)
+            time.sleep(float(rng.exponential(0.002)))  # arrivals overlap running work
+            for tt in list(pending):
+                r = srv.poll(tt)
+                if r is not None:
+                    got[pending.pop(tt)] = r
+        t_bad2 = srv.submit(bad_dup)
+        drain(srv, pending, got, time.time() + 60)
+        rb1, rb2 = None, None
+        deadline = time.time() + 30
+        while (rb1 is None or rb2 is None) and time.time() < deadline:
+            rb1 = rb1 or srv.poll(t_bad1)
+            rb2 = rb2 or srv.poll(t_bad2)
+            time.sleep(0.001)
+        rc = srv.stop()
+    assert rc == B.OK, B.strerror(rc)
+    assert not pending and len(got) == len(states)
+    for k in range(len(states)):
+        ln, nodes, status = got[k]
+        assert status == 1, (k, status)
+        assert ln == want_len[k] and (nodes == want_nodes[k]).all(), k
+    assert rb1[2] == B.EUNSOLVABLE and rb1[0] == -1
+    assert rb2[2] == B.EINVAL and rb2[0] == -1
+    print("server stats: %s" % B.last_stats(), flush=True)
+
+
+def test_full_ring_reports_eagain_and_recovers(B):
+    print("case: server ring of 64 requests, 100 submitted without collecting", flush=True)
+    s1, l1, n1 = load_golden("c1_walk40")
+    with B.Server(max_inflight=16, ring_capacity=64) as srv:
+        tickets = []
+        refused = 0
+        for i in range(100):
+            t = srv.submit(s1[i % 64])
+            if t is None:
+                refused += 1
+            else:
+                tickets.append((t, i % 64))
+        assert refused > 0 and len(tickets) == 64
+        res = {}
+        deadline = time.time() + 60
+        while len(res) < len(tickets) and time.time() < deadline:
+            for t, k in tickets:
+                if t not in res:
+                    r = srv.poll(t)
+                    if r is not None:
+                        res[t] = (k, r)
+            time.sleep(0.0005)
+        assert len(res) == len(tickets)
+        t2 = srv.submit(s1[5])
+        assert t2 is not None
+        r2 = None
+        deadline = time.time() + 30
+        while r2 is None and time.time() < deadline:
+            r2 = srv.poll(t2)
+        assert srv.stop() == B.OK
+    for t, (k, r) in res.items():
+        assert r is not None and r[2] == 1 and r[0] == l1[k] and (r[1] == n1[k]).all()
+    assert r2[0] == l1[5] and (r2[1] == n1[5]).all()
