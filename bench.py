@@ -164,6 +164,9 @@ def main():
 
     def run_mode(mode, steps, warmup):
         bpida.set_option("mode", MODES[mode])
+        if mode == "plain":  # the plain path always runs with its own defaults
+            for k in ("frontier_depth", "lds_stack_capacity", "max_workgroups"):
+                bpida.set_option(k, -1 if k != "max_workgroups" else 0)
 
         def step():
             rc = bpida.solve_device(d_states, d_len, d_nodes, width=width, stream=stream)
@@ -251,7 +254,11 @@ def main():
         out["compare"] = {"skipped": "plain path not timed on batches above 512 states"}
     elif not args.no_compare:
         other = "plain" if args.mode == "batched" else "batched"
+        saved = {k: bpida.get_option(k) for k in ("frontier_depth", "lds_stack_capacity",
+                                                  "max_workgroups")}
         odt, _, _ = run_mode(other, 1, 1)
+        for k, v in saved.items():
+            bpida.set_option(k, v)
         out["compare"] = {"mode": other, "value": round(nodes_per_step / odt, 1),
                           "unit": "nodes/s", "ms_per_step": round(odt * 1e3, 3),
                           "instances_per_s": round(n / odt, 2), "steps": 1, "warmup": 1,
