@@ -37,9 +37,11 @@ extern "C" {
 /* Columns of the per-limit node-count matrix: limit h0 + 2j goes in column j. */
 #define BPIDA_MAX_THRESHOLDS 64
 
-/* Widths supported by the search kernels. */
-#define BPIDA_MIN_WIDTH 4
-#define BPIDA_MAX_WIDTH 4
+/* Board widths: 3 (8-puzzle), 4 (15-puzzle), 5 (24-puzzle).  The batched
+ * mode takes all three (4 bits per tile for 3x3 and 4x4, 5 bits for 5x5);
+ * the plain mode and the server take width 4 only. */
+#define BPIDA_MIN_WIDTH 3
+#define BPIDA_MAX_WIDTH 5
 
 enum bpida_status {
   BPIDA_OK = 0,
@@ -61,7 +63,8 @@ enum bpida_status {
  * Solve n_instances puzzles given in host memory (BPIDA*, Alg. 1).
  *
  * states     host, n_instances * width * width bytes (layout above).
- * width      side of the board; 4 (the 15-puzzle).
+ * width      side of the board: 3, 4 or 5 (batched mode), 4 (plain mode;
+ *            another width is BPIDA_EINVAL there).
  * out_len    host, n_instances int32: optimal solution length, or -1 for an
  *            instance that is invalid, unsolvable or stopped by a limit.
  * out_nodes_per_threshold
@@ -77,6 +80,16 @@ enum bpida_status {
  */
 int bpida_solve(const uint8_t *states, int32_t n_instances, int32_t width, int32_t *out_len,
                 uint64_t *out_nodes_per_threshold);
+
+/*
+ * As bpida_solve for a batch that mixes board widths, always in batched mode
+ * (one persistent launch for all of them).  widths: host, n int32 in 3..5.
+ * states: host, the instances' bytes back to back (instance i takes
+ * widths[i]^2 bytes).  Outputs as in bpida_solve.  5x5 instances need an LDS
+ * ring of at least 512 entries (the default), 3x3 of 256.
+ */
+int bpida_solve_mixed(const uint8_t *states, const int32_t *widths, int32_t n_instances,
+                      int32_t *out_len, uint64_t *out_nodes_per_threshold);
 
 /*
  * As bpida_solve, with every buffer in device memory of the current device:
@@ -122,7 +135,7 @@ int bpida_solve_device_async(const uint8_t *d_states, int32_t n_instances, int32
  * read at start.  The launch ends when the host has asked to stop and every
  * admitted request is answered, or after budget_ms.
  */
-int bpida_server_start(int32_t width, int32_t max_inflight, int32_t ring_capacity,
+int bpida_server_start(int32_t width /* 4 */, int32_t max_inflight, int32_t ring_capacity,
                        void *hip_stream);
 
 /*

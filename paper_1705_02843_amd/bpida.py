@@ -17,7 +17,7 @@ OK, EINVAL, EUNSOLVABLE, ELIMIT, ENOMEM, EDEVICE, EINTERNAL, EAGAIN = 0, -1, -2,
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbpida.so")
 
-EXPORTS = ("bpida_solve", "bpida_solve_device", "bpida_solve_device_async", "bpida_set_option",
+EXPORTS = ("bpida_solve", "bpida_solve_mixed", "bpida_solve_device", "bpida_solve_device_async", "bpida_set_option",
            "bpida_get_option", "bpida_last_stats", "bpida_strerror", "bpida_server_start",
            "bpida_server_submit", "bpida_server_poll", "bpida_server_stop")
 
@@ -37,6 +37,9 @@ def _load() -> ctypes.CDLL:
     lib.bpida_solve.argtypes = [P(ctypes.c_uint8), ctypes.c_int32, ctypes.c_int32,
                                 P(ctypes.c_int32), P(ctypes.c_uint64)]
     lib.bpida_solve.restype = ctypes.c_int
+    lib.bpida_solve_mixed.argtypes = [P(ctypes.c_uint8), P(ctypes.c_int32), ctypes.c_int32,
+                                      P(ctypes.c_int32), P(ctypes.c_uint64)]
+    lib.bpida_solve_mixed.restype = ctypes.c_int
     lib.bpida_solve_device.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.bpida_solve_device.restype = ctypes.c_int
@@ -102,6 +105,23 @@ def solve_raw(states: np.ndarray, width: int = 4):
     rc = lib.bpida_solve(st.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), n, width,
                          out_len.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                          nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    return int(rc), out_len, nodes
+
+
+def solve_mixed_raw(states_list):
+    """Batch of states of mixed widths (a list of uint8 vectors of w*w
+    entries).  Returns (rc, out_len int32[n], nodes uint64[n, 64])."""
+    widths = np.array([int(round(len(s) ** 0.5)) for s in states_list], np.int32)
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(s, np.uint8).reshape(-1)
+                                                for s in states_list]) if states_list
+                                else np.zeros(0, np.uint8))
+    n = len(states_list)
+    out_len = np.full(n, -7, np.int32)
+    nodes = np.zeros((n, MAX_THRESHOLDS), np.uint64)
+    rc = lib.bpida_solve_mixed(flat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                               widths.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n,
+                               out_len.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
     return int(rc), out_len, nodes
 
 

@@ -17,6 +17,7 @@
 // advances the limit by 2 and seeds the instance's subtree roots again.
 #include <limits.h>
 
+#include "bpida_board.h"
 #include "bpida_internal.h"
 #include "bpida_round.h"
 
@@ -53,7 +54,9 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t v) {
 }
 
 // Returns false only if the ring stayed full for the whole bounded wait.
-__device__ bool q_push(const BatchArgs& A, uint64_t tile, uint16_t meta, int count, int inst) {
+// `hi` is stored only for 5x5 chunks (wide).
+__device__ bool q_push(const BatchArgs& A, uint64_t tile, uint64_t hi, uint16_t meta, int count,
+                       int inst, bool wide) {
   const int lane = threadIdx.x;
   QueueCtl* q = A.q;
   const uint64_t mask = A.qmask;
@@ -79,6 +82,7 @@ __device__ bool q_push(const BatchArgs& A, uint64_t tile, uint16_t meta, int cou
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   QChunk* c = A.slots + (pos & mask);
   c->tiles[lane] = tile;
+  if (wide) c->hi[lane] = hi;
   c->meta[lane] = meta;
   if (lane == 0) {
     c->inst = inst;
@@ -92,8 +96,8 @@ __device__ bool q_push(const BatchArgs& A, uint64_t tile, uint16_t meta, int cou
 // Takes a consumer ticket if `ticket` holds none, then checks whether that
 // ticket's chunk has arrived.  Returns true with the chunk, or false (the
 // ticket is kept for the next call).
-__device__ bool q_take(const BatchArgs& A, uint64_t& ticket, uint64_t& tile, uint16_t& meta,
-                       int& count, int& inst) {
+__device__ bool q_take(const BatchArgs& A, uint64_t& ticket, uint64_t& tile, uint64_t& hi,
+                       uint16_t& meta, int& count, int& inst) {
   const int lane = threadIdx.x;
   QueueCtl* q = A.q;
   const uint64_t mask = A.qmask;
@@ -107,6 +111,7 @@ __device__ bool q_take(const BatchArgs& A, uint64_t& ticket, uint64_t& tile, uin
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const QChunk* c = A.slots + (ticket & mask);
   tile = c->tiles[lane];
+  hi = c->hi[lane];
   meta = c->meta[lane];
   count = wave_bcast(c->count);
   inst = wave_bcast(c->inst);
@@ -124,21 +129,23 @@ __device__ bool q_take(const BatchArgs& A, uint64_t& ticket, uint64_t& tile, uin
 // unit so that the limit cannot complete while seeding.  Returns true if the
 // guard's release brought the instance's outstanding count to zero, i.e. the
 // caller must complete the limit itself.
-// `stage_t` / `stage_m` are 64 entries of LDS the caller does not use while
-// seeding (its stack ring is empty whenever a limit is seeded).
-__device__ bool seed_limit(const BatchArgs& A, int i, uint64_t* stage_t, uint16_t* stage_m) {
+// `stage` (128 u64) and `stage_m` (64 u16) are LDS the caller does not use
+// while seeding (its stack ring is empty whenever a limit is seeded).
+__device__ bool seed_limit(const BatchArgs& A, int i, uint64_t* stage, uint16_t* stage_m) {
   const int lane = threadIdx.x;
   InstState* S = A.is + i;
   const int L = S->limit;
+  const bool wide = S->width == 5;
   if (lane == 0) __hip_atomic_store(&S->outstanding, 1, __ATOMIC_RELAXED, AGENT);
-  const Node* roots = A.tree + S->root_off;
+  const NodeW* roots = A.tree + S->root_off;
   const int nroots = S->nroots;
   int fm = INT_MAX;
   bool full = false;
   for (int base = 0; base < nroots && !full; base += 64) {
     const int r = base + lane;
-    Node R;
-    R.tiles = 0;
+    NodeW R;
+    R.lo = 0;
+    R.hi = 0;
     R.meta = 0;
     R.f = 0;
     bool keep = false;
@@ -151,20 +158,20 @@ __device__ bool seed_limit(const BatchArgs& A, int i, uint64_t* stage_t, uint16_
     const int cnt = __popcll(km);
     if (cnt == 0) continue;
     // compact the kept roots into lanes 0..cnt-1 through LDS
-    uint64_t* s_t = stage_t;
-    uint16_t* s_m = stage_m;
     const int off = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
                                               __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
     if (keep) {
-      s_t[off] = R.tiles;
-      s_m[off] = stack_meta((int)(R.meta & 15u), (int)((R.meta >> 4) & 7u), L - (int)R.f);
+      stage[off] = R.lo;
+      stage[64 + off] = R.hi;
+      stage_m[off] = stack_meta((int)(R.meta & 31u), (int)((R.meta >> 5) & 7u), L - (int)R.f);
     }
     WAVE_SYNC();
-    const uint64_t t = s_t[lane];
-    const uint16_t m = s_m[lane];
+    const uint64_t t = stage[lane];
+    const uint64_t th = stage[64 + lane];
+    const uint16_t m = stage_m[lane];
     WAVE_SYNC();
     if (lane == 0) __hip_atomic_fetch_add(&S->outstanding, 1, __ATOMIC_RELAXED, AGENT);
-    if (!q_push(A, t, m, cnt, i)) {
+    if (!q_push(A, t, th, m, cnt, i, wide)) {
       full = true;  // the remaining roots are dropped; the call reports BPIDA_ENOMEM
       if (lane == 0) {
         __hip_atomic_fetch_add(&S->outstanding, -1, __ATOMIC_RELAXED, AGENT);
@@ -205,7 +212,7 @@ __device__ void emit_result(const BatchArgs& A, int i, int status) {
 // Completes the current limit of instance i (its outstanding count is zero
 // and this wave observed it), then advances it.  Loops while a new limit
 // has no queued work.
-__device__ void complete_limit(const BatchArgs& A, int i, uint64_t* stage_t, uint16_t* stage_m) {
+__device__ void complete_limit(const BatchArgs& A, int i, uint64_t* stage, uint16_t* stage_m) {
   const int lane = threadIdx.x;
   InstState* S = A.is + i;
   for (;;) {
@@ -254,7 +261,7 @@ __device__ void complete_limit(const BatchArgs& A, int i, uint64_t* stage_t, uin
       return;
     }
     __syncthreads();
-    if (!seed_limit(A, i, stage_t, stage_m)) return;
+    if (!seed_limit(A, i, stage, stage_m)) return;
   }
 }
 
@@ -306,13 +313,14 @@ __device__ Inst wave_ingest4(const uint8_t* src) {
 // base[], interior nodes binned by f in hist_lds (256 entries of LDS).
 // Returns the first root's index inside base; the root count is
 // walks[blank][depth].
-__device__ int64_t wave_split4(const Inst& I, int depth, const int32_t* walks, Node* base,
+__device__ int64_t wave_split4(const Inst& I, int depth, const int32_t* walks, NodeW* base,
                                uint32_t* hist_lds, uint32_t* hist_out, int32_t* goal_g_out) {
   const int lane = threadIdx.x;
   for (int k = lane; k < kHistBins; k += 64) hist_lds[k] = 0;
   if (lane == 0) {
-    Node r;
-    r.tiles = I.tiles;
+    NodeW r;
+    r.lo = I.tiles;
+    r.hi = 0;
     r.meta = node_meta(I.blank, 4, 0, I.h0);
     r.f = (uint32_t)I.h0;
     base[0] = r;
@@ -327,21 +335,22 @@ __device__ int64_t wave_split4(const Inst& I, int depth, const int32_t* walks, N
     int64_t fill = next;
     for (int k0 = 0; k0 < cnt; k0 += 64) {
       const int k = k0 + lane;
-      Node nd;
-      nd.tiles = 0;
+      NodeW nd;
+      nd.lo = 0;
+      nd.hi = 0;
       nd.meta = 0;
       nd.f = 0;
       if (k < cnt) nd = base[lvl + k];
-      const int b = (int)(nd.meta & 15u), fb = (int)((nd.meta >> 4) & 7u);
+      const int b = (int)(nd.meta & 31u), fb = (int)((nd.meta >> 5) & 7u);
       const int g = (int)((nd.meta >> 8) & 255u), h = (int)((nd.meta >> 16) & 255u);
       if (k < cnt) {
         atomicAdd(&hist_lds[min(g + h, kHistBins - 1)], 1u);
-        if (nd.tiles == kGoal4) gmin = min(gmin, g);
+        if (nd.lo == kGoal4) gmin = min(gmin, g);
       }
       for (int a = 0; a < 4; ++a) {
         const bool ok = k < cnt && ((kMoveMask4 >> (4 * b + a)) & 1ull) && a != fb;
         const int nn = (b + (a == 0 ? -4 : a == 1 ? -1 : a == 2 ? 1 : 4)) & 15;
-        const uint32_t t = (uint32_t)(nd.tiles >> (4 * nn)) & 15u;
+        const uint32_t t = (uint32_t)(nd.lo >> (4 * nn)) & 15u;
         const int sh = (a == 0 || a == 3) ? 2 : 0;
         const uint32_t idx = (((t >> sh) & 3u) << 2) | (((uint32_t)nn >> sh) & 3u);
         const int h2 = h + (((kDhTable4 >> (16 * a + idx)) & 1ull) ? 1 : -1);
@@ -349,8 +358,9 @@ __device__ int64_t wave_split4(const Inst& I, int depth, const int32_t* walks, N
         const int off = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
         if (ok && fill + off < next + lc[d + 1]) {  // the level's exact size bounds it
-          Node c;
-          c.tiles = nd.tiles + ((uint64_t)t << (4 * b)) - ((uint64_t)t << (4 * nn));
+          NodeW c;
+          c.lo = nd.lo + ((uint64_t)t << (4 * b)) - ((uint64_t)t << (4 * nn));
+          c.hi = 0;
           c.meta = node_meta(nn, 3 - a, g + 1, h2);
           c.f = (uint32_t)(g + 1 + h2);
           base[fill + off] = c;
@@ -440,9 +450,9 @@ __device__ void admitter_loop(const BatchArgs& A, uint64_t* st, uint16_t* sm, ui
     S.goals = 0;
     S.root_off = (int64_t)slot * V.stride;
     S.nroots = 0;
-    S.pad = 0;
+    S.width = 4;
     if (I.status == 0) {
-      Node* base = const_cast<Node*>(A.tree) + (int64_t)slot * V.stride;
+      NodeW* base = const_cast<NodeW*>(A.tree) + (int64_t)slot * V.stride;
       const int64_t r0 = wave_split4(I, V.depth, V.walks, base, hist_lds,
                                      const_cast<uint32_t*>(A.hist) + (size_t)slot * kHistBins,
                                      const_cast<int32_t*>(A.goal_g) + slot);
@@ -462,7 +472,7 @@ __device__ void admitter_loop(const BatchArgs& A, uint64_t* st, uint16_t* sm, ui
 // Adds this workgroup's counts for the unit of instance i it held and
 // releases the unit; completes the limit if it was the last unit.
 __device__ void release_unit(const BatchArgs& A, int i, uint64_t expanded, int goals, int fmin,
-                             uint64_t* stage_t, uint16_t* stage_m) {
+                             uint64_t* stage, uint16_t* stage_m) {
   const int lane = threadIdx.x;
   InstState* S = A.is + i;
   fmin = wave_min(fmin);
@@ -473,25 +483,122 @@ __device__ void release_unit(const BatchArgs& A, int i, uint64_t expanded, int g
     if (fmin != INT_MAX) __hip_atomic_fetch_min(&S->fmin, fmin, __ATOMIC_RELAXED, AGENT);
     last = __hip_atomic_fetch_add(&S->outstanding, -1, __ATOMIC_ACQ_REL, AGENT) == 1;
   }
-  if (wave_bcast(last)) complete_limit(A, i, stage_t, stage_m);
+  if (wave_bcast(last)) complete_limit(A, i, stage, stage_m);
 }
 
 // ---------------------------------------------------------------------------
 // The persistent kernel.
 // ---------------------------------------------------------------------------
+// Per-workgroup run counters.
+struct WgCounters {
+  uint64_t rounds = 0, pushes = 0, voluntary = 0;
+};
+
+// Searches one unit (the chunk already in LDS entries [0, cnt)) of an
+// instance of width W until its stack is empty: BPDFS rounds, with spills
+// to the queue when LDS would overflow and donations to waiting workgroups.
 // NPL = nodes popped per round: 16 (lane l expands node l/4 with move l%4,
-// Alg. 1's thread -> action map) or 64 (one node per lane, four moves each).
+// Alg. 1's thread -> action map; width 4 only) or 64 (one node per lane,
+// four moves each).  Returns false if the time budget ran out (abandoned).
+template <int W, int CAP, int NPL>
+__device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board<W>::S* st,
+                         uint16_t* sm, int cnt, WgCounters& wc, uint32_t& tick, uint64_t deadline,
+                         uint64_t& expanded, int& goals, int& fmin) {
+  static_assert(NPL == 64 || W == 4, "16-node rounds are the 4x4 map");
+  static_assert((CAP & (CAP - 1)) == 0 && CAP >= (NPL == 64 ? 256 : 128), "ring size");
+  using S = typename Board<W>::S;
+  const int lane = threadIdx.x;
+  QueueCtl* q = A.q;
+  const bool wide = W == 5;
+  // largest growth of one round: a popped node has at most 4 children
+  constexpr int kGrow = NPL == 16 ? 32 : 3 * 64;
+  const LaneMap M = make_lane_map(lane);
+  int smax = INT_MIN;
+  int top = cnt, bot = 0;
+  while (top != bot) {
+    int avail = top - bot;
+    ++tick;
+    if ((tick & 1023u) == 0 && wall_clock64() > deadline) {
+      if (lane == 0) atomicOr(&q->err, 8);
+      return false;
+    }
+    if (avail + kGrow > CAP) {
+      // LDS would overflow: move the 64 oldest entries to the queue
+      const int p = (bot + lane) & (CAP - 1);
+      const S t = st[p];
+      const uint16_t m = sm[p];
+      WAVE_SYNC();
+      if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
+      if (q_push(A, (uint64_t)t, wide ? (uint64_t)((unsigned __int128)t >> 64) : 0ull, m, 64, inst,
+                 wide)) {
+        wc.pushes += 1;
+      } else if (lane == 0) {
+        __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
+        atomicOr(&q->err, 2);  // entries dropped: the call reports BPIDA_ENOMEM
+      }
+      bot += 64;
+      avail -= 64;
+    } else if (avail >= 32 && (tick & 31u) == 0) {
+      // donation when workgroups wait on tickets no queued chunk covers: the
+      // oldest min(128, avail) entries (the shallowest, largest subtrees) are
+      // split alternately, so donor and receiver each keep about half
+      int want = 0;
+      if (lane == 0) want = (int64_t)(ld_relaxed(&q->head) - ld_relaxed(&q->tail)) > 0;
+      if (wave_bcast(want)) {
+        const int w = min(avail, 128) & ~1;
+        const int h = w >> 1;
+        const int pg = (bot + 2 * lane) & (CAP - 1);
+        const int pk = (bot + 2 * lane + 1) & (CAP - 1);
+        const S tg = st[pg], tk = st[pk];
+        const uint16_t mg = sm[pg], mk = sm[pk];
+        WAVE_SYNC();
+        if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
+        if (q_push(A, (uint64_t)tg, wide ? (uint64_t)((unsigned __int128)tg >> 64) : 0ull, mg, h,
+                   inst, wide)) {
+          wc.pushes += 1;
+          wc.voluntary += 1;
+          if (lane < h) {
+            const int pn = (bot + h + lane) & (CAP - 1);
+            st[pn] = tk;
+            sm[pn] = mk;
+          }
+          WAVE_SYNC();
+          bot += h;
+          avail -= h;
+        } else if (lane == 0) {
+          __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
+        }
+      }
+    }
+    const int kp = min(avail, NPL);
+    if constexpr (NPL == 16) {
+      top = bp_round<CAP>((uint64_t*)st, sm, top, kp, limit, M, goals, fmin);
+    } else {
+      top = bp_round64w<W, CAP>(st, sm, top, kp, goals, smax);
+    }
+    expanded += (uint64_t)kp;
+    wc.rounds += 1;
+  }
+  if (NPL == 64) {
+    const int sm_w = wave_max(smax);
+    fmin = sm_w == INT_MIN ? INT_MAX : limit - sm_w;
+  }
+  return true;
+}
+
+// The persistent kernel.  LDS: a 10*CAP-byte ring, CAP entries of u64 tiles
+// + u16 meta for widths 3 and 4, CAP/2 entries of 128-bit tiles + u16 meta
+// for width 5; the width is read per chunk from the instance.
 template <int CAP, int NPL>
 __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
   static_assert((CAP & (CAP - 1)) == 0 && CAP >= 128, "ring size");
   static_assert(NPL == 16 || NPL == 64, "nodes per round");
-  static_assert(NPL == 16 || CAP >= 512, "ring too small for 64-node rounds");
-  // largest growth of one round: a popped node has at most 4 children
-  constexpr int kGrow = NPL == 16 ? 32 : 3 * 64;
-  __shared__ uint64_t st[CAP];
-  __shared__ uint16_t sm[CAP];
+  static_assert(NPL == 16 || CAP >= 256, "ring too small for 64-node rounds");
+  __shared__ __attribute__((aligned(16))) uint64_t lds[(10 * CAP) / 8];
+  uint64_t* st = lds;                          // widths 3, 4: CAP tiles
+  uint16_t* sm = (uint16_t*)(lds + CAP);       // CAP (or CAP/2) meta words
+  unsigned __int128* st5 = (unsigned __int128*)lds;  // width 5: CAP/2 tiles
   const int lane = threadIdx.x;
-  const LaneMap M = make_lane_map(lane);
   QueueCtl* q = A.q;
 
   if (A.server) {
@@ -515,14 +622,10 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
     if (seed_limit(A, i, st, sm)) complete_limit(A, i, st, sm);
   }
 
-  uint64_t rounds = 0, searched = 0, pushes = 0, pops = 0, voluntary = 0;
+  WgCounters wc;
+  uint64_t searched = 0, pops = 0;
   uint64_t t_work = 0, t_queue = 0, t_idle = 0;
   uint64_t t_mark = wall_clock64();
-  int inst = -1, limit = 0;
-  uint64_t expanded = 0;
-  int goals = 0, fmin = INT_MAX;  // 16-node rounds track fmin per lane
-  int smax = INT_MIN;             // 64-node rounds track the largest pruned slack
-  int top = 0, bot = 0;
   bool idle = false;
   uint64_t idle_since = 0, idle_act = 0;
   uint32_t tick = 0;
@@ -531,161 +634,104 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
   const uint64_t deadline = wall_clock64() + A.budget_ticks;
 
   for (;;) {
-    if (top == bot) {
-      {
-        const uint64_t now = wall_clock64();
-        t_work += now - t_mark;
-        t_mark = now;
-      }
-      if (inst >= 0) {
-        if (NPL == 64) {
-          const int sm_w = wave_max(smax);
-          fmin = sm_w == INT_MIN ? INT_MAX : limit - sm_w;
-        }
-        release_unit(A, inst, expanded, goals, fmin, st, sm);
-        searched += expanded;
-        inst = -1;
-      }
-      uint64_t t;
-      uint16_t m;
-      int cnt, ci;
-      if (!q_take(A, ticket, t, m, cnt, ci)) {
-        if (ld_relaxed(&q->remaining) <= 0) break;
-        const uint64_t now = wall_clock64();
-        // queue activity seen by this idle workgroup (lane 0's view)
-        uint64_t act = 0;
-        if (lane == 0) act = ld_relaxed(&q->head) + ld_relaxed(&q->tail);
-        act = (uint64_t)(uint32_t)wave_bcast((int)(uint32_t)act);
-        if (!idle) {
-          idle = true;
-          idle_since = now;
-          idle_act = act;
-          backoff = 1;
-        } else if (act != idle_act) {
-          idle_since = now;  // the queue moved: work is being shared
-          idle_act = act;
-        } else if (now - idle_since > A.idle_ticks || now > deadline) {
-          // no queue activity for the whole watchdog period although
-          // instances remain, or the run's time budget is spent
-          if (lane == 0) atomicOr(&q->err, now > deadline ? 8 : 4);
-          break;
-        }
-        // exponential backoff (64 .. 1024 x 64 clocks) keeps idle
-        // workgroups from flooding the queue's cache lines
-        for (int k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(64);
-        backoff = min(backoff * 2, 8);
-        {
-          const uint64_t now2 = wall_clock64();
-          t_idle += now2 - t_mark;
-          t_mark = now2;
-        }
-        continue;
-      }
-      if (idle) {
-        idle = false;
+    uint64_t t, th;
+    uint16_t m;
+    int cnt, inst;
+    if (!q_take(A, ticket, t, th, m, cnt, inst)) {
+      if (ld_relaxed(&q->remaining) <= 0) break;
+      const uint64_t now = wall_clock64();
+      // queue activity seen by this idle workgroup (lane 0's view)
+      uint64_t act = 0;
+      if (lane == 0) act = ld_relaxed(&q->head) + ld_relaxed(&q->tail);
+      act = (uint64_t)(uint32_t)wave_bcast((int)(uint32_t)act);
+      if (!idle) {
+        idle = true;
+        idle_since = now;
+        idle_act = act;
         backoff = 1;
+      } else if (act != idle_act) {
+        idle_since = now;  // the queue moved: work is being shared
+        idle_act = act;
+      } else if (now - idle_since > A.idle_ticks || now > deadline) {
+        // no queue activity for the whole watchdog period although
+        // instances remain, or the run's time budget is spent
+        if (lane == 0) atomicOr(&q->err, now > deadline ? 8 : 4);
+        break;
       }
-      pops += 1;
-      {
-        const uint64_t now = wall_clock64();
-        t_queue += now - t_mark;
-        t_mark = now;
-      }
-      inst = ci;
-      limit = A.is[inst].limit;
-      expanded = 0;
-      goals = 0;
-      fmin = INT_MAX;
-      smax = INT_MIN;
-      top = cnt;
-      bot = 0;
+      // exponential backoff (1 .. 8 x 4096 clocks) keeps idle workgroups
+      // from flooding the queue's cache lines
+      for (int k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(64);
+      backoff = min(backoff * 2, 8);
+      const uint64_t now2 = wall_clock64();
+      t_idle += now2 - t_mark;
+      t_mark = now2;
+      continue;
+    }
+    idle = false;
+    backoff = 1;
+    pops += 1;
+    {
+      const uint64_t now = wall_clock64();
+      t_queue += now - t_mark;
+      t_mark = now;
+    }
+    const int limit = A.is[inst].limit;
+    const int width = A.is[inst].width;
+    uint64_t expanded = 0;
+    int goals = 0, fmin = INT_MAX;
+    bool ok = true;
+    if (width == 4) {
       if (lane < cnt) {
         st[lane] = t;
         sm[lane] = m;
       }
       WAVE_SYNC();
-    }
-    int avail = top - bot;
-    ++tick;
-    if ((tick & 1023u) == 0 && wall_clock64() > deadline) {
-      if (lane == 0) atomicOr(&q->err, 8);
-      break;  // abandon: the call reports BPIDA_EINTERNAL
-    }
-    if (avail + kGrow > CAP) {
-      // LDS would overflow: move the 64 oldest entries to the queue
-      const int p = (bot + lane) & (CAP - 1);
-      const uint64_t t = st[p];
-      const uint16_t m = sm[p];
-      WAVE_SYNC();
-      if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
-      if (q_push(A, t, m, 64, inst)) {
-        pushes += 1;
-      } else {
-        if (lane == 0) {
-          __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
-          atomicOr(&q->err, 2);  // entries dropped: the call reports BPIDA_ENOMEM
+      ok = run_unit<4, CAP, NPL>(A, inst, limit, st, sm, cnt, wc, tick, deadline, expanded, goals,
+                                 fmin);
+    } else if (width == 3) {
+      if constexpr (CAP >= 256) {
+        if (lane < cnt) {
+          st[lane] = t;
+          sm[lane] = m;
         }
-      }
-      bot += 64;
-      avail -= 64;
-    } else if (avail >= 32 && (tick & 31u) == 0) {
-      // donation to idle workgroups when the queue holds fewer chunks than
-      // there are idle workgroups.  The oldest min(128, avail) entries (the
-      // shallowest, largest subtrees) are split alternately: donor and
-      // receiver each keep about half of that work.
-      int want = 0;
-      if (lane == 0) {
-        // consumers waiting on tickets that no queued chunk covers yet
-        const int64_t waiting = (int64_t)(ld_relaxed(&q->head) - ld_relaxed(&q->tail));
-        want = waiting > 0;
-      }
-      if (wave_bcast(want)) {
-        const int w = min(avail, 128) & ~1;
-        const int h = w >> 1;
-        const int pg = (bot + 2 * lane) & (CAP - 1);
-        const int pk = (bot + 2 * lane + 1) & (CAP - 1);
-        const uint64_t tg = st[pg], tk = st[pk];
-        const uint16_t mg = sm[pg], mk = sm[pk];
         WAVE_SYNC();
-        if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
-        if (q_push(A, tg, mg, h, inst)) {
-          pushes += 1;
-          voluntary += 1;
-          if (lane < h) {
-            const int pn = (bot + h + lane) & (CAP - 1);
-            st[pn] = tk;
-            sm[pn] = mk;
-          }
-          WAVE_SYNC();
-          bot += h;
-          avail -= h;
-        } else if (lane == 0) {
-          __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
+        ok = run_unit<3, CAP, 64>(A, inst, limit, st, sm, cnt, wc, tick, deadline, expanded, goals,
+                                  fmin);
+      }
+    } else {
+      if constexpr (CAP / 2 >= 256) {
+        if (lane < cnt) {
+          st5[lane] = (unsigned __int128)t | ((unsigned __int128)th << 64);
+          sm[lane] = m;
         }
+        WAVE_SYNC();
+        ok = run_unit<5, CAP / 2, 64>(A, inst, limit, st5, sm, cnt, wc, tick, deadline, expanded,
+                                      goals, fmin);
       }
     }
-    const int kp = min(avail, NPL);
-    if (NPL == 16) top = bp_round<CAP>(st, sm, top, kp, limit, M, goals, fmin);
-    else top = bp_round64<CAP>(st, sm, top, kp, goals, smax);
-    expanded += (uint64_t)kp;
-    rounds += 1;
+    if (!ok) break;
+    const uint64_t now = wall_clock64();
+    t_work += now - t_mark;
+    t_mark = now;
+    release_unit(A, inst, expanded, goals, fmin, st, sm);
+    searched += expanded;
   }
   if (lane == 0) {
-    atomicAdd((unsigned long long*)&q->rounds, (unsigned long long)rounds);
+    atomicAdd((unsigned long long*)&q->rounds, (unsigned long long)wc.rounds);
     atomicAdd((unsigned long long*)&q->searched, (unsigned long long)searched);
-    atomicAdd((unsigned long long*)&q->pushes, (unsigned long long)pushes);
+    atomicAdd((unsigned long long*)&q->pushes, (unsigned long long)wc.pushes);
     atomicAdd((unsigned long long*)&q->pops, (unsigned long long)pops);
     atomicAdd((unsigned long long*)&q->t_work, (unsigned long long)t_work);
     atomicAdd((unsigned long long*)&q->t_queue, (unsigned long long)t_queue);
     atomicAdd((unsigned long long*)&q->t_idle, (unsigned long long)t_idle);
-    atomicAdd((unsigned long long*)&q->voluntary, (unsigned long long)voluntary);
+    atomicAdd((unsigned long long*)&q->voluntary, (unsigned long long)wc.voluntary);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Set-up: per-instance state, queue sequence numbers and counters.
 // ---------------------------------------------------------------------------
-__global__ void batch_setup_kernel(BatchArgs A, const Inst* __restrict__ inst,
+__global__ void batch_setup_kernel(BatchArgs A, const InstW* __restrict__ inst,
                                    const int64_t* __restrict__ root_off,
                                    const int32_t* __restrict__ nroots) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -701,7 +747,7 @@ __global__ void batch_setup_kernel(BatchArgs A, const Inst* __restrict__ inst,
     S.goals = 0;
     S.root_off = root_off[k];
     S.nroots = nroots[k];
-    S.pad = 0;
+    S.width = inst[k].width;
     if (S.done == 0 && S.limit > A.max_limit) S.done = -3;  // BPIDA_ELIMIT
     A.is[k] = S;
     if (S.done == 0) atomicAdd(&A.q->remaining, 1);
@@ -724,6 +770,180 @@ __global__ void batch_status_kernel(const InstState* __restrict__ is, int n,
   st[k] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Ingest and root split of the batched path, any width.
+// ---------------------------------------------------------------------------
+
+// One thread per instance: validate (a permutation of 0..w*w-1 whose parity
+// matches the blank's distance from cell 0), pack, Manhattan h0.  States are
+// w*w bytes at byte_off[i] (or i*w*w); widths[i] (or `width`) per instance.
+__global__ void ingestw_kernel(const uint8_t* __restrict__ states, const int64_t* __restrict__ byte_off,
+                               const int32_t* __restrict__ widths, int width, int n,
+                               InstW* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int w = widths ? widths[i] : width;
+  InstW r;
+  r.lo = 0;
+  r.hi = 0;
+  r.blank = 0;
+  r.h0 = 0;
+  r.status = -1;  // BPIDA_EINVAL
+  r.width = w;
+  if (w < 3 || w > 5) {
+    out[i] = r;
+    return;
+  }
+  const int nn = w * w;
+  const int bits = w == 5 ? 5 : 4;
+  const uint8_t* s = states + (byte_off ? byte_off[i] : (int64_t)i * nn);
+  uint32_t seen = 0;
+  bool ok = true;
+  unsigned __int128 word = 0;
+  int blank = 0, h = 0;
+  uint32_t inv = 0;
+  for (int p = 0; p < nn; ++p) {
+    const uint32_t v = s[p];
+    if (v >= (uint32_t)nn || ((seen >> v) & 1u)) ok = false;
+    seen |= 1u << (v & 31u);
+    if (v == 0) blank = p;
+    word |= (unsigned __int128)(v & 31u) << (bits * p);
+    if (v != 0 && v < (uint32_t)nn) {
+      const int dr = p / w - (int)v / w, dc = p % w - (int)v % w;
+      h += (dr < 0 ? -dr : dr) + (dc < 0 ? -dc : dc);
+    }
+    for (int q = 0; q < p; ++q) inv ^= (uint32_t)(s[q] > v);
+  }
+  if (ok) {
+    const uint32_t bpar = (uint32_t)(blank / w + blank % w) & 1u;
+    r.status = inv == bpar ? 0 : -2;  // BPIDA_EUNSOLVABLE
+    r.lo = (uint64_t)word;
+    r.hi = (uint64_t)(word >> 64);
+    r.blank = blank;
+    r.h0 = h;
+  }
+  out[i] = r;
+}
+
+hipError_t launch_ingestw(const uint8_t* d_states, const int64_t* d_byte_off, const int32_t* d_widths,
+                          int width, int n, InstW* d_inst, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ingestw_kernel, dim3((n + 127) / 128), dim3(128), 0, s, d_states, d_byte_off,
+                     d_widths, width, n, d_inst);
+  return hipGetLastError();
+}
+
+constexpr int kSplitThreadsW = 256;
+
+// The parent-pruned tree of one instance to depth D, level after level
+// (CreateRootSet, no duplicate elimination); the workgroup's instance has
+// width W.  Level sizes come from the walk-count table of that width.
+template <int W>
+__device__ void split_impl(const InstW& I, int depth, const int32_t* walks, NodeW* base,
+                           uint32_t* h_lds, int32_t* fill, int32_t* gmin, int32_t* err,
+                           int64_t* lvl_out) {
+  using B = Board<W>;
+  using S = typename B::S;
+  const int32_t* lc = walks + (size_t)I.blank * (kMaxDepth + 1);
+  if (threadIdx.x == 0) {
+    NodeW r;
+    r.lo = I.lo;
+    r.hi = I.hi;
+    r.meta = node_meta(I.blank, 4, 0, I.h0);
+    r.f = (uint32_t)I.h0;
+    base[0] = r;
+  }
+  __syncthreads();
+  int64_t lvl = 0;
+  for (int d = 0; d < depth; ++d) {
+    const int cnt = lc[d];
+    const int64_t next = lvl + cnt;
+    for (int k = threadIdx.x; k < cnt; k += kSplitThreadsW) {
+      const NodeW nd = base[lvl + k];
+      const S s = (S)nd.lo | (W == 5 ? ((S)nd.hi << 64) : (S)0);
+      const uint32_t b = nd.meta & 31u, fb = (nd.meta >> 5) & 7u;
+      const int g = (int)((nd.meta >> 8) & 255u), h = (int)((nd.meta >> 16) & 255u);
+      atomicAdd(&h_lds[min(g + h, kHistBins - 1)], 1u);
+      if (s == B::goal()) atomicMin(gmin, g);
+      const uint32_t lm = B::legal(b) & ~(1u << fb);
+      for (int a = 0; a < 4; ++a) {
+        if (!((lm >> a) & 1u)) continue;
+        const int delta = a == 0 ? -W : a == 1 ? -1 : a == 2 ? 1 : W;
+        const uint32_t nn = b + (uint32_t)delta;
+        const uint32_t t = (uint32_t)(s >> (B::BITS * nn)) & B::MASK;
+        const bool vert = a == 0 || a == 3;
+        const uint32_t ct = vert ? t / W : t % W, cn = vert ? nn / W : nn % W;
+        const int up = (int)((B::table(a) >> (ct * W + cn)) & 1u);
+        const int h2 = h + (up ? 1 : -1);
+        const S cs = s + ((S)t << (B::BITS * b)) - ((S)t << (B::BITS * nn));
+        NodeW c;
+        c.lo = (uint64_t)cs;
+        c.hi = W == 5 ? (uint64_t)((unsigned __int128)cs >> 64) : 0ull;
+        c.meta = node_meta((int)nn, 3 - a, g + 1, h2);
+        c.f = (uint32_t)(g + 1 + h2);
+        const int slot = atomicAdd(fill, 1);
+        if (slot < lc[d + 1]) base[next + slot] = c;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (*fill != lc[d + 1]) atomicOr(err, 1);
+      *fill = 0;
+    }
+    lvl = next;
+    __syncthreads();
+  }
+  *lvl_out = lvl;
+}
+
+// One workgroup of 256 threads per instance; the instance's region is
+// tree_off[i] (or i * stride).  `walks` = [width - 3][cell][length] counts.
+__global__ __launch_bounds__(kSplitThreadsW) void splitw_kernel(
+    const InstW* __restrict__ inst, int depth, const int64_t* __restrict__ tree_off, int64_t stride,
+    const int32_t* __restrict__ walks, NodeW* __restrict__ tree, uint32_t* __restrict__ hist,
+    int32_t* __restrict__ goal_g, int32_t* __restrict__ err, int64_t* __restrict__ root_off,
+    int32_t* __restrict__ nroots) {
+  const int i = blockIdx.x;
+  const InstW I = inst[i];
+  __shared__ uint32_t h_lds[kHistBins];
+  __shared__ int32_t fill;
+  __shared__ int32_t gmin;
+  for (int k = threadIdx.x; k < kHistBins; k += kSplitThreadsW) h_lds[k] = 0;
+  if (threadIdx.x == 0) {
+    gmin = INT_MAX;
+    fill = 0;
+  }
+  const int64_t region = tree_off ? tree_off[i] : (int64_t)i * stride;
+  NodeW* base = tree + region;
+  int64_t lvl = 0;
+  if (I.status == 0) {
+    const int32_t* wk = walks + (size_t)(I.width - 3) * kWalkStride;
+    if (I.width == 3) split_impl<3>(I, depth, wk, base, h_lds, &fill, &gmin, err, &lvl);
+    else if (I.width == 4) split_impl<4>(I, depth, wk, base, h_lds, &fill, &gmin, err, &lvl);
+    else split_impl<5>(I, depth, wk, base, h_lds, &fill, &gmin, err, &lvl);
+  } else {
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < kHistBins; k += kSplitThreadsW) hist[(size_t)i * kHistBins + k] = h_lds[k];
+  if (threadIdx.x == 0) {
+    goal_g[i] = gmin;
+    root_off[i] = region + lvl;
+    nroots[i] = I.status == 0
+                    ? walks[(size_t)(I.width - 3) * kWalkStride + (size_t)I.blank * (kMaxDepth + 1) + depth]
+                    : 0;
+  }
+}
+
+hipError_t launch_splitw(const InstW* d_inst, int n, int depth, const int64_t* d_tree_off,
+                         int64_t stride, const int32_t* d_walks, NodeW* d_tree, uint32_t* d_hist,
+                         int32_t* d_goal_g, int32_t* d_err, int64_t* d_root_off, int32_t* d_nroots,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(splitw_kernel, dim3(n), dim3(kSplitThreadsW), 0, s, d_inst, depth, d_tree_off,
+                     stride, d_walks, d_tree, d_hist, d_goal_g, d_err, d_root_off, d_nroots);
+  return hipGetLastError();
+}
+
 // Server set-up: queue sequence numbers, free instance slots, one sentinel in
 // `remaining` (cleared by the admitter when the server shuts down).
 __global__ void server_setup_kernel(BatchArgs A) {
@@ -743,7 +963,7 @@ hipError_t launch_server_setup(const BatchArgs& A, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch_setup(const BatchArgs& A, const Inst* d_inst, const int64_t* d_root_off,
+hipError_t launch_batch_setup(const BatchArgs& A, const InstW* d_inst, const int64_t* d_root_off,
                               const int32_t* d_nroots, hipStream_t s) {
   const int64_t work = std::max<int64_t>((int64_t)A.qmask + 1, A.n);
   hipLaunchKernelGGL(batch_setup_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, A,
@@ -775,7 +995,8 @@ static int occupancy_t() {
 
 // Supported (ring capacity, nodes per round) pairs.
 #define BATCH_CONFIGS(X) \
-  X(128, 16) X(256, 16) X(512, 16) X(1024, 16) X(2048, 16) X(512, 64) X(1024, 64) X(2048, 64)
+  X(128, 16) X(256, 16) X(512, 16) X(1024, 16) X(2048, 16) X(256, 64) X(512, 64) X(1024, 64) \
+  X(2048, 64)
 
 hipError_t launch_batch4(int lds_cap, int npl, int grid, const BatchArgs& A, hipStream_t s) {
   if (grid <= 0) return hipSuccess;

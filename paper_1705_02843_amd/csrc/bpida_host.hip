@@ -80,7 +80,9 @@ struct Workspace {
   bool arch_ok = false;
   DevBuf inst, tree, tree_off, hist, goal_g, err, cursor, part, spill_t, spill_m, res;
   DevBuf qctl, qseq, qslots, istate, root_off, nroots, status, walks;
-  int32_t h_walks[16][kMaxDepth + 1];  // non-backtracking walk counts per start cell and length
+  // non-backtracking walk counts per width (3, 4, 5), start cell and length
+  int32_t h_walks[3][kWalkCells][kMaxDepth + 1];
+  DevBuf treew, winst, tree_offw, widths, byte_off;
   DevBuf h2d_states, out_len, out_nodes;
   LimitResult* h_res = nullptr;  // pinned
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -94,28 +96,32 @@ int map_err(hipError_t e) {
   return BPIDA_EDEVICE;
 }
 
-// Number of non-backtracking blank walks of each length 0..depth from `blank`
-// (the exact size of each level of the split tree).
-void level_sizes(int blank, int depth, int32_t* out) {
-  int64_t cur[16][5] = {};
+// Number of non-backtracking blank walks of each length 0..depth from cell
+// `blank` of a width-w board (the exact size of each split-tree level).
+void level_sizes_w(int w, int blank, int depth, int32_t* out) {
+  int64_t cur[kWalkCells][5] = {};
   cur[blank][4] = 1;
   for (int d = 0; d <= depth; ++d) {
-    int64_t tot = 0, nxt[16][5] = {};
-    for (int c = 0; c < 16; ++c)
+    int64_t tot = 0, nxt[kWalkCells][5] = {};
+    for (int c = 0; c < w * w; ++c)
       for (int fb = 0; fb < 5; ++fb) {
         const int64_t m = cur[c][fb];
         if (!m) continue;
         tot += m;
+        const int r = c / w, col = c % w;
         for (int a = 0; a < 4; ++a) {
-          if (!((kMoveMask4 >> (4 * c + a)) & 1ull) || a == fb) continue;
-          const int n = c + (a == 0 ? -4 : a == 1 ? -1 : a == 2 ? 1 : 4);
+          const bool ok = a == 0 ? r > 0 : a == 1 ? col > 0 : a == 2 ? col < w - 1 : r < w - 1;
+          if (!ok || a == fb) continue;
+          const int n = c + (a == 0 ? -w : a == 1 ? -1 : a == 2 ? 1 : w);
           nxt[n][3 - a] += m;
         }
       }
-    out[d] = (int32_t)tot;
+    out[d] = (int32_t)std::min<int64_t>(tot, INT32_MAX);
     memcpy(cur, nxt, sizeof cur);
   }
 }
+
+void level_sizes(int blank, int depth, int32_t* out) { level_sizes_w(4, blank, depth, out); }
 
 int ensure_device() {
   int dev = 0;
@@ -141,7 +147,9 @@ int ensure_device() {
     return BPIDA_ENOMEM;
   if (hipEventCreate(&g_ws.ev0) != hipSuccess || hipEventCreate(&g_ws.ev1) != hipSuccess)
     return BPIDA_EDEVICE;
-  for (int c = 0; c < 16; ++c) level_sizes(c, kMaxDepth, g_ws.h_walks[c]);
+  memset(g_ws.h_walks, 0, sizeof g_ws.h_walks);
+  for (int w = 3; w <= 5; ++w)
+    for (int c = 0; c < w * w; ++c) level_sizes_w(w, c, kMaxDepth, g_ws.h_walks[w - 3][c]);
   if (g_ws.walks.ensure(sizeof g_ws.h_walks) != hipSuccess) return BPIDA_ENOMEM;
   if (hipMemcpy(g_ws.walks.p, g_ws.h_walks, sizeof g_ws.h_walks, hipMemcpyHostToDevice) != hipSuccess)
     return BPIDA_EDEVICE;
@@ -159,14 +167,15 @@ int depth_for(const Options& O) {
 }
 
 int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes, hipStream_t st,
-                const Options& O);
+                const Options& O, int width = 4, const int32_t* h_widths = nullptr);
 
 // The plain BPIDA* driver (Alg. 1 as printed: one search launch per f-limit
 // and instance, one root per workgroup, no dynamic balancing).  All buffers
 // are device buffers; outputs are written on `st`.
 int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes, hipStream_t st,
-              const Options& O) {
-  if (O.mode == kModeBatched) return run_batched(d_states, n, d_len, d_nodes, st, O);
+              const Options& O, int width = 4) {
+  if (O.mode == kModeBatched) return run_batched(d_states, n, d_len, d_nodes, st, O, width);
+  if (width != 4) return BPIDA_EINVAL;  // the plain path is the 15-puzzle kernel
   Workspace& W = g_ws;
   uint64_t stats[16] = {0};
   hipError_t e;
@@ -215,7 +224,8 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
   HIPCHK(W.err.ensure(sizeof(int32_t)));
   HIPCHK(hipMemcpyAsync(W.tree_off.p, off.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st));
   HIPCHK(launch_zero_i32(W.err.as<int32_t>(), 1, st));
-  HIPCHK(launch_split4(W.inst.as<Inst>(), n, D, W.tree_off.as<int64_t>(), 0, W.walks.as<int32_t>(),
+  HIPCHK(launch_split4(W.inst.as<Inst>(), n, D, W.tree_off.as<int64_t>(), 0,
+                       W.walks.as<int32_t>() + kWalkStride,
                        W.tree.as<Node>(), W.hist.as<uint32_t>(), W.goal_g.as<int32_t>(),
                        W.err.as<int32_t>(), nullptr, nullptr, st));
   int32_t split_err = 0;
@@ -292,9 +302,32 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
 // Enqueues the whole batched solve on `st`; per-instance status (1 solved,
 // < 0 bpida_status) lands in d_status.  No host synchronisation, no copy to
 // the host: the sequence can be recorded into a HIP graph.
+// Split-tree nodes per instance of width w at depth D (the largest level
+// total over start cells) and the largest root count.
+void tree_size(const Workspace& W, int w, int D, int64_t* stride, int64_t* max_roots) {
+  *stride = 0;
+  *max_roots = 0;
+  for (int c = 0; c < w * w; ++c) {
+    int64_t tot = 0;
+    for (int d = 0; d <= D; ++d) tot += W.h_walks[w - 3][c][d];
+    *stride = std::max(*stride, tot);
+    *max_roots = std::max<int64_t>(*max_roots, W.h_walks[w - 3][c][D]);
+  }
+}
+
+// Ring capacity a width needs with this ring option (64-node rounds need
+// 256 entries; 5x5 entries take two slots of the LDS budget).
+// 3x3 and 5x5 instances always run 64-node rounds; a 5x5 state takes two
+// ring entries, so its ring holds cap / 2 of them.
+bool ring_fits(int w, int cap) {
+  if (w == 4) return true;
+  if (w == 3) return cap >= 256;
+  return cap / 2 >= 256;
+}
+
 int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
                     int32_t* d_status, hipStream_t st, const Options& O, bool timed,
-                    int64_t* grid_out) {
+                    int64_t* grid_out, int width = 4, const int32_t* h_widths = nullptr) {
   Workspace& W = g_ws;
   hipError_t e;
 #define HIPCHK(x)              \
@@ -311,34 +344,55 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
   const int D = depth_for(O);
   const int npl = (int)O.nodes_per_round;
   const int cap = cap_for(O, npl);
-  if (n == 0) return BPIDA_OK;
+  const int per_cu = batch4_max_blocks_per_cu(cap, npl);
+  if (per_cu <= 0) return BPIDA_EINVAL;  // unsupported capacity for this round width
 
-  // Every buffer size below depends on n and D only, and no value travels
-  // back to the host before the persistent launch: the whole solve is one
-  // stream-ordered sequence of kernels.
-  int64_t stride = 0, max_roots = 0;
-  for (int c = 0; c < 16; ++c) {
-    int64_t tot = 0;
-    for (int d = 0; d <= D; ++d) tot += W.h_walks[c][d];
-    stride = std::max(stride, tot);
-    max_roots = std::max<int64_t>(max_roots, W.h_walks[c][D]);
+  // Every buffer size below depends on n, the widths and D only, and no
+  // value travels back to the host before the persistent launch: the whole
+  // solve is one stream-ordered sequence of kernels.
+  int64_t tree_nodes = 0, seed_chunks = 0, stride = 0;
+  if (!h_widths) {
+    int64_t mr = 0;
+    tree_size(W, width, D, &stride, &mr);
+    if (!ring_fits(width, cap)) return BPIDA_EINVAL;
+    tree_nodes = stride * n;
+    seed_chunks = (int64_t)n * ((mr + kQChunk - 1) / kQChunk);
+  } else {
+    std::vector<int64_t> toff((size_t)n), boff((size_t)n);
+    int64_t bytes = 0;
+    for (int i = 0; i < n; ++i) {
+      const int w = h_widths[i];
+      if (w < 3 || w > 5 || !ring_fits(w, cap)) return BPIDA_EINVAL;
+      int64_t sw = 0, mr = 0;
+      tree_size(W, w, D, &sw, &mr);
+      toff[i] = tree_nodes;
+      boff[i] = bytes;
+      tree_nodes += sw;
+      bytes += (int64_t)w * w;
+      seed_chunks += (mr + kQChunk - 1) / kQChunk;
+    }
+    HIPCHK(W.widths.ensure(sizeof(int32_t) * (size_t)n));
+    HIPCHK(W.byte_off.ensure(sizeof(int64_t) * (size_t)n));
+    HIPCHK(W.tree_offw.ensure(sizeof(int64_t) * (size_t)n));
+    HIPCHK(hipMemcpyAsync(W.widths.p, h_widths, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(W.byte_off.p, boff.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(W.tree_offw.p, toff.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st));
   }
-  const int64_t seed_chunks = (int64_t)n * ((max_roots + kQChunk - 1) / kQChunk);
-  HIPCHK(W.inst.ensure(sizeof(Inst) * (size_t)n));
-  HIPCHK(W.tree.ensure(sizeof(Node) * (size_t)(stride * n)));
+  HIPCHK(W.winst.ensure(sizeof(InstW) * (size_t)n));
+  HIPCHK(W.treew.ensure(sizeof(NodeW) * (size_t)tree_nodes));
   HIPCHK(W.hist.ensure(sizeof(uint32_t) * kHistBins * (size_t)n));
   HIPCHK(W.goal_g.ensure(sizeof(int32_t) * (size_t)n));
   HIPCHK(W.err.ensure(sizeof(int32_t)));
   HIPCHK(W.root_off.ensure(sizeof(int64_t) * (size_t)n));
   HIPCHK(W.nroots.ensure(sizeof(int32_t) * (size_t)n));
-  HIPCHK(launch_ingest4(d_states, n, W.inst.as<Inst>(), st));
+  HIPCHK(launch_ingestw(d_states, h_widths ? W.byte_off.as<int64_t>() : nullptr,
+                        h_widths ? W.widths.as<int32_t>() : nullptr, width, n, W.winst.as<InstW>(), st));
   HIPCHK(launch_zero_i32(W.err.as<int32_t>(), 1, st));
-  HIPCHK(launch_split4(W.inst.as<Inst>(), n, D, nullptr, stride, W.walks.as<int32_t>(),
-                       W.tree.as<Node>(), W.hist.as<uint32_t>(), W.goal_g.as<int32_t>(),
-                       W.err.as<int32_t>(), W.root_off.as<int64_t>(), W.nroots.as<int32_t>(), st));
+  HIPCHK(launch_splitw(W.winst.as<InstW>(), n, D, h_widths ? W.tree_offw.as<int64_t>() : nullptr,
+                       stride, W.walks.as<int32_t>(), W.treew.as<NodeW>(), W.hist.as<uint32_t>(),
+                       W.goal_g.as<int32_t>(), W.err.as<int32_t>(), W.root_off.as<int64_t>(),
+                       W.nroots.as<int32_t>(), st));
 
-  const int per_cu = batch4_max_blocks_per_cu(cap, npl);
-  if (per_cu <= 0) return BPIDA_EINVAL;  // unsupported capacity for this round width
   int64_t grid = (int64_t)per_cu * W.num_cu;
   if (O.max_workgroups > 0) grid = std::min<int64_t>(grid, O.max_workgroups);
   uint64_t qcap = 64;
@@ -357,7 +411,7 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
   A.slots = W.qslots.as<QChunk>();
   A.qmask = qcap - 1;
   A.is = W.istate.as<InstState>();
-  A.tree = W.tree.as<Node>();
+  A.tree = W.treew.as<NodeW>();
   A.hist = W.hist.as<uint32_t>();
   A.goal_g = W.goal_g.as<int32_t>();
   A.out_len = d_len;
@@ -368,7 +422,7 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
   A.max_limit = (int)(O.max_threshold >= 0 ? std::min<int64_t>(O.max_threshold, kMaxLimit) : kMaxLimit);
   A.idle_ticks = (uint64_t)O.watchdog_ms * (uint64_t)W.wall_khz;
   A.budget_ticks = (uint64_t)O.budget_ms * (uint64_t)W.wall_khz;
-  HIPCHK(launch_batch_setup(A, W.inst.as<Inst>(), W.root_off.as<int64_t>(), W.nroots.as<int32_t>(), st));
+  HIPCHK(launch_batch_setup(A, W.winst.as<InstW>(), W.root_off.as<int64_t>(), W.nroots.as<int32_t>(), st));
   if (timed) HIPCHK(hipEventRecord(W.ev0, st));
   HIPCHK(launch_batch4(cap, npl, (int)grid, A, st));
   if (timed) HIPCHK(hipEventRecord(W.ev1, st));
@@ -380,7 +434,7 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
 
 // The batched driver: enqueue, then wait and read the status back.
 int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes, hipStream_t st,
-                const Options& O) {
+                const Options& O, int width, const int32_t* h_widths) {
   Workspace& W = g_ws;
   uint64_t stats[16] = {0};
   hipError_t e;
@@ -398,7 +452,8 @@ int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_node
   }
   HIPCHK(W.status.ensure(sizeof(int32_t) * (size_t)n));
   int64_t grid = 0;
-  int rc0 = enqueue_batched(d_states, n, d_len, d_nodes, W.status.as<int32_t>(), st, O, true, &grid);
+  int rc0 = enqueue_batched(d_states, n, d_len, d_nodes, W.status.as<int32_t>(), st, O, true, &grid,
+                            width, h_widths);
   if (rc0 != BPIDA_OK) return rc0;
   std::vector<int32_t> status((size_t)n);
   QueueCtl qc;
@@ -452,13 +507,52 @@ extern "C" int bpida_solve(const uint8_t* states, int32_t n_instances, int32_t w
     if (rc != BPIDA_OK) return rc;
     Workspace& W = g_ws;
     hipStream_t st = nullptr;
-    if (W.h2d_states.ensure(n * 16) != hipSuccess || W.out_len.ensure(n * sizeof(int32_t)) != hipSuccess ||
+    const size_t bytes = n * (size_t)width * (size_t)width;
+    if (W.h2d_states.ensure(bytes) != hipSuccess || W.out_len.ensure(n * sizeof(int32_t)) != hipSuccess ||
         W.out_nodes.ensure(n * BPIDA_MAX_THRESHOLDS * sizeof(uint64_t)) != hipSuccess)
       return BPIDA_ENOMEM;
-    if (hipMemcpyAsync(W.h2d_states.p, states, n * 16, hipMemcpyHostToDevice, st) != hipSuccess)
+    if (hipMemcpyAsync(W.h2d_states.p, states, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
       return BPIDA_EDEVICE;
     rc = run_plain(W.h2d_states.as<uint8_t>(), (int)n, W.out_len.as<int32_t>(),
-                   W.out_nodes.as<uint64_t>(), st, O);
+                   W.out_nodes.as<uint64_t>(), st, O, width);
+    if (hipMemcpyAsync(out_len, W.out_len.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(out_nodes_per_threshold, W.out_nodes.p, n * BPIDA_MAX_THRESHOLDS * sizeof(uint64_t),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return BPIDA_EDEVICE;
+    return rc;
+  } catch (const std::bad_alloc&) {
+    return BPIDA_ENOMEM;
+  } catch (...) {
+    return BPIDA_EINTERNAL;
+  }
+}
+
+extern "C" int bpida_solve_mixed(const uint8_t* states, const int32_t* widths, int32_t n_instances,
+                                 int32_t* out_len, uint64_t* out_nodes_per_threshold) {
+  try {
+    if (!states || !widths || !out_len || !out_nodes_per_threshold || n_instances < 0) return BPIDA_EINVAL;
+    size_t bytes = 0;
+    for (int32_t i = 0; i < n_instances; ++i) {
+      if (widths[i] < BPIDA_MIN_WIDTH || widths[i] > BPIDA_MAX_WIDTH) return BPIDA_EINVAL;
+      bytes += (size_t)widths[i] * (size_t)widths[i];
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    Options O = g_opt;
+    O.mode = kModeBatched;
+    const size_t n = (size_t)n_instances;
+    if (n == 0) return BPIDA_OK;
+    int rc = ensure_device();
+    if (rc != BPIDA_OK) return rc;
+    Workspace& W = g_ws;
+    hipStream_t st = nullptr;
+    if (W.h2d_states.ensure(bytes) != hipSuccess || W.out_len.ensure(n * sizeof(int32_t)) != hipSuccess ||
+        W.out_nodes.ensure(n * BPIDA_MAX_THRESHOLDS * sizeof(uint64_t)) != hipSuccess)
+      return BPIDA_ENOMEM;
+    if (hipMemcpyAsync(W.h2d_states.p, states, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+      return BPIDA_EDEVICE;
+    rc = run_batched(W.h2d_states.as<uint8_t>(), (int)n, W.out_len.as<int32_t>(),
+                     W.out_nodes.as<uint64_t>(), st, O, 0, widths);
     if (hipMemcpyAsync(out_len, W.out_len.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipMemcpyAsync(out_nodes_per_threshold, W.out_nodes.p, n * BPIDA_MAX_THRESHOLDS * sizeof(uint64_t),
                        hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -482,7 +576,7 @@ extern "C" int bpida_solve_device(const uint8_t* d_states, int32_t n_instances, 
     if (n_instances == 0) return BPIDA_OK;
     int rc = ensure_device();
     if (rc != BPIDA_OK) return rc;
-    return run_plain(d_states, n_instances, d_len, d_nodes, (hipStream_t)hip_stream, O);
+    return run_plain(d_states, n_instances, d_len, d_nodes, (hipStream_t)hip_stream, O, width);
   } catch (const std::bad_alloc&) {
     return BPIDA_ENOMEM;
   } catch (...) {
@@ -528,7 +622,7 @@ void free_server_host(Server& V) {
 extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t ring_capacity,
                                   void* hip_stream) {
   try {
-    if (check_opts(width) != BPIDA_OK || max_inflight < 1 || max_inflight > (1 << 16) ||
+    if (width != 4 || max_inflight < 1 || max_inflight > (1 << 16) ||
         ring_capacity < 1 || ring_capacity > (1 << 20))
       return BPIDA_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
@@ -548,12 +642,7 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     if (O.max_workgroups > 0) grid = std::min<int64_t>(grid, O.max_workgroups);
     if (grid < 2) return BPIDA_EINVAL;  // one admitter plus at least one searcher
     int64_t stride = 0, max_roots = 0;
-    for (int c = 0; c < 16; ++c) {
-      int64_t tot = 0;
-      for (int d = 0; d <= D; ++d) tot += W.h_walks[c][d];
-      stride = std::max(stride, tot);
-      max_roots = std::max<int64_t>(max_roots, W.h_walks[c][D]);
-    }
+    tree_size(W, 4, D, &stride, &max_roots);
     const int64_t S = max_inflight;
     uint64_t ring = 64;
     while (ring < (uint64_t)ring_capacity) ring <<= 1;
@@ -566,7 +655,7 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     if (V.qctl.ensure(sizeof(QueueCtl)) != hipSuccess || V.qseq.ensure(sizeof(uint64_t) * qcap) != hipSuccess ||
         V.qslots.ensure(sizeof(QChunk) * qcap) != hipSuccess ||
         V.istate.ensure(sizeof(InstState) * S) != hipSuccess ||
-        V.tree.ensure(sizeof(Node) * S * stride) != hipSuccess ||
+        V.tree.ensure(sizeof(NodeW) * S * stride) != hipSuccess ||
         V.hist.ensure(sizeof(uint32_t) * kHistBins * S) != hipSuccess ||
         V.goal_g.ensure(sizeof(int32_t) * S) != hipSuccess ||
         V.out_len.ensure(sizeof(int32_t) * S) != hipSuccess ||
@@ -605,7 +694,7 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     A.slots = V.qslots.as<QChunk>();
     A.qmask = qcap - 1;
     A.is = V.istate.as<InstState>();
-    A.tree = V.tree.as<Node>();
+    A.tree = V.tree.as<NodeW>();
     A.hist = V.hist.as<uint32_t>();
     A.goal_g = V.goal_g.as<int32_t>();
     A.out_len = V.out_len.as<int32_t>();
@@ -624,7 +713,7 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     A.srv.stride = stride;
     A.srv.busy = V.busy.as<int32_t>();
     A.srv.ticket = V.ticket.as<uint64_t>();
-    A.srv.walks = W.walks.as<int32_t>();
+    A.srv.walks = W.walks.as<int32_t>() + kWalkStride;
     A.srv.admitter = V.admitter.as<int32_t>();
     A.srv.in_flight = V.inflight.as<int32_t>();
     if (launch_zero_words(V.qctl.p, sizeof(QueueCtl), V.stream) != hipSuccess ||
@@ -730,7 +819,7 @@ extern "C" int bpida_solve_device_async(const uint8_t* d_states, int32_t n_insta
     int64_t grid = 0;
     Options Ob = O;
     Ob.mode = kModeBatched;
-    rc = enqueue_batched(d_states, n_instances, d_len, d_nodes, d_status, st, Ob, false, &grid);
+    rc = enqueue_batched(d_states, n_instances, d_len, d_nodes, d_status, st, Ob, false, &grid, width);
     g_no_alloc = false;
     return rc;
   } catch (const std::bad_alloc&) {

@@ -55,7 +55,7 @@ constexpr uint64_t make_dh_table4() {
 constexpr uint64_t kDhTable4 = make_dh_table4();
 
 // A node of the split tree, and a subtree root of the search.
-//   meta bits 0..3 blank cell, 4..6 forbidden move (inverse of the move that
+//   meta bits 0..4 blank cell, 5..7 forbidden move (inverse of the move that
 //   produced the node; 4 = none), 8..15 g, 16..23 h.
 struct alignas(16) Node {
   uint64_t tiles;
@@ -64,8 +64,24 @@ struct alignas(16) Node {
 };
 
 __host__ __device__ inline uint32_t node_meta(int blank, int forbid, int g, int h) {
-  return (uint32_t)blank | ((uint32_t)forbid << 4) | ((uint32_t)g << 8) | ((uint32_t)h << 16);
+  return (uint32_t)blank | ((uint32_t)forbid << 5) | ((uint32_t)g << 8) | ((uint32_t)h << 16);
 }
+
+// Split-tree node of the batched path, any width (5x5 states take 125 bits).
+struct alignas(8) NodeW {
+  uint64_t lo, hi;  // packed state: bits 0..63, 64..127
+  uint32_t meta;    // as Node
+  uint32_t f;
+};
+
+// Ingest result of the batched path, any width.
+struct InstW {
+  uint64_t lo, hi;
+  int32_t blank;
+  int32_t h0;
+  int32_t status;  // bpida_status
+  int32_t width;
+};
 
 // Ingest result per instance.
 struct Inst {
@@ -102,6 +118,8 @@ struct LimitResult {
 constexpr int kHistBins = 256;  // f values 0..255 of the split tree's interior
 constexpr int kMaxLimit = 255;  // slack and f fit in 8 bits
 constexpr int kMaxDepth = 16;  // deepest root split
+constexpr int kWalkCells = 25;  // walk-count table: [width - 3][cell][length]
+constexpr int kWalkStride = kWalkCells * (kMaxDepth + 1);
 
 // ---------------------------------------------------------------------------
 // Batched persistent search (bpida_batch.hip).
@@ -110,7 +128,8 @@ constexpr int kQChunk = 64;  // stack entries per queue chunk
 
 // One queue slot: up to 64 stack entries of one instance at its current limit.
 struct alignas(128) QChunk {
-  uint64_t tiles[kQChunk];
+  uint64_t tiles[kQChunk];  // packed states, bits 0..63
+  uint64_t hi[kQChunk];     // bits 64..127 (5x5 only)
   uint16_t meta[kQChunk];
   int32_t inst;
   int32_t count;
@@ -127,7 +146,7 @@ struct InstState {
   int32_t goals;        // goals expanded at the current limit
   int64_t root_off;     // first root of this instance in the split tree buffer
   int32_t nroots;
-  int32_t pad;
+  int32_t width;        // board width 3, 4 or 5
 };
 
 // Queue control block and run counters.  The fields that many workgroups
@@ -178,7 +197,7 @@ struct ServerArgs {
   int64_t stride;       // split-tree nodes per slot
   int32_t* busy;        // per slot: 1 while a request occupies it
   uint64_t* ticket;     // per slot: request ticket
-  const int32_t* walks; // walk counts per start cell and length
+  const int32_t* walks; // walk counts per start cell and length, width 4
   int32_t* admitter;    // 0 until a workgroup takes the admitter role
   int32_t* in_flight;   // admitted, not yet answered
 };
@@ -189,7 +208,7 @@ struct BatchArgs {
   QChunk* slots;
   uint64_t qmask;      // capacity - 1 (capacity a power of two)
   InstState* is;
-  const Node* tree;
+  const NodeW* tree;
   const uint32_t* hist;
   const int32_t* goal_g;
   int32_t* out_len;
@@ -204,8 +223,14 @@ struct BatchArgs {
 
 hipError_t launch_server_setup(const BatchArgs& A, hipStream_t s);
 
-hipError_t launch_batch_setup(const BatchArgs& A, const Inst* d_inst, const int64_t* d_root_off,
+hipError_t launch_batch_setup(const BatchArgs& A, const InstW* d_inst, const int64_t* d_root_off,
                               const int32_t* d_nroots, hipStream_t s);
+hipError_t launch_ingestw(const uint8_t* d_states, const int64_t* d_byte_off, const int32_t* d_widths,
+                          int width, int n, InstW* d_inst, hipStream_t s);
+hipError_t launch_splitw(const InstW* d_inst, int n, int depth, const int64_t* d_tree_off,
+                         int64_t stride, const int32_t* d_walks, NodeW* d_tree, uint32_t* d_hist,
+                         int32_t* d_goal_g, int32_t* d_err, int64_t* d_root_off, int32_t* d_nroots,
+                         hipStream_t s);
 hipError_t launch_batch4(int lds_cap, int npl, int grid, const BatchArgs& A, hipStream_t s);
 hipError_t launch_batch_status(const InstState* d_is, int n, const QueueCtl* d_q,
                                const int32_t* d_split_err, int32_t* d_status, hipStream_t s);

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kSplitThreads) void split4_kernel(
     const int64_t next = lvl + cnt;
     for (int k = threadIdx.x; k < cnt; k += kSplitThreads) {
       const Node nd = base[lvl + k];
-      const int b = nd.meta & 15, fb = (nd.meta >> 4) & 7;
+      const int b = nd.meta & 31, fb = (nd.meta >> 5) & 7;
       const int g = (nd.meta >> 8) & 255, h = (nd.meta >> 16) & 255;
       atomicAdd(&h_lds[min(g + h, kHistBins - 1)], 1u);
       if (nd.tiles == kGoal4) atomicMin(&gmin, g);
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
     }
     if (lane == 0) {
       st[0] = R.tiles;
-      sm[0] = (uint16_t)((R.meta & 0x7Fu) | ((uint32_t)(limit - (int)R.f) << 8));
+      sm[0] = (uint16_t)((R.meta & 0xFFu) | ((uint32_t)(limit - (int)R.f) << 8));
     }
     WAVE_SYNC();
     int top = 1, bot = 0, sp = 0;

@@ -276,7 +276,7 @@ def test_batched_uneven_batch_exact(opts):
 def test_batched_rejects_ring_too_small_for_64_node_rounds(opts):
     B = opts
     set_mode(B, "batched")
-    B.set_option("lds_stack_capacity", 256)
+    B.set_option("lds_stack_capacity", 128)  # 64-node rounds need 256 entries
     states, _, _ = load_golden("c1_walk40")
     rc, _, _ = B.solve_raw(states[:2])
     assert rc == B.EINVAL

@@ -1,0 +1,107 @@
+"""Batched search on 3x3 and 5x5 boards and on mixed-width batches.
+
+Bit-exact against the CPU oracle run live on the same states (the oracle
+handles every width).  5x5 states come from walks short enough for the
+oracle to finish in seconds, plus the easy part of the 60-move workload.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1705_02843_amd import bpida
+    keys = ("mode", "nodes_per_round", "lds_stack_capacity", "frontier_depth", "max_workgroups")
+    saved = {k: bpida.get_option(k) for k in keys}
+    bpida.set_option("mode", 1)
+    yield bpida
+    for k, v in saved.items():
+        bpida.set_option(k, v)
+
+
+def oracle_of(states, w):
+    from oracle import oracle
+    r = oracle.solve(np.stack(states), w, nthreads=8)
+    assert r.rc == 0
+    return r
+
+
+def five_by_five_states(n_short=24):
+    from paper_1705_02843_amd import instances as I
+    rng = np.random.Generator(np.random.PCG64(55))
+    out = [I.random_walk(rng, 5, k)[0] for k in range(2, 2 + n_short)]
+    d = I.c4_mixed(n3=1, n4=1, n5=16)
+    # the 60-move states whose optimum the oracle reaches within h0 + 10
+    from oracle import oracle
+    for s in d[5][0]:
+        r = oracle.solve(s[None], 5, max_limit=oracle.manhattan(s, 5) + 10)
+        if r.rc == 0:
+            out.append(s)
+    return out
+
+
+def check(B, got_len, got_nodes, want, tag):
+    bad = np.nonzero((got_len != want.length) | (got_nodes != want.nodes).any(axis=1))[0]
+    assert bad.size == 0, "%s: %d differ, first %d: %s vs %s" % (
+        tag, bad.size, bad[0], got_nodes[bad[0], :8], want.nodes[bad[0], :8])
+
+
+@pytest.mark.parametrize("depth", [0, 4, 8])
+def test_width3_exact(B, depth):
+    from paper_1705_02843_amd import instances as I
+    print("case: 3x3, 512 states, depth %d" % depth, flush=True)
+    s3, _ = I.c4_mixed(n3=512, n4=1, n5=1)[3]
+    want = oracle_of(list(s3), 3)
+    B.set_option("frontier_depth", depth)
+    rc, ln, nodes = B.solve_raw(s3, 3)
+    assert rc == B.OK, B.strerror(rc)
+    check(B, ln, nodes, want, "3x3")
+
+
+@pytest.mark.parametrize("cap", [512, 1024, 2048])
+def test_width5_exact(B, cap):
+    print("case: 5x5, short walks + easy 60-move states, ring %d" % cap, flush=True)
+    states = five_by_five_states()
+    want = oracle_of(states, 5)
+    B.set_option("lds_stack_capacity", cap)
+    rc, ln, nodes = B.solve_raw(np.stack(states), 5)
+    assert rc == B.OK, B.strerror(rc)
+    check(B, ln, nodes, want, "5x5")
+
+
+def test_mixed_widths_one_launch_exact(B):
+    from paper_1705_02843_amd import instances as I
+    print("case: mixed 3x3 / 4x4 / 5x5 batch in one launch", flush=True)
+    d = I.c4_mixed(n3=96, n4=48, n5=1)
+    s3, s4 = list(d[3][0]), list(d[4][0][:48])
+    s4 = [s for s in s4 if I.manhattan_filter_value(s, 4) <= 30][:24]
+    s5 = five_by_five_states(12)
+    w3, w4, w5 = oracle_of(s3, 3), oracle_of(s4, 4), oracle_of(s5, 5)
+    rng = np.random.default_rng(4)
+    items = [(s, w3, i) for i, s in enumerate(s3)] + [(s, w4, i) for i, s in enumerate(s4)] + \
+        [(s, w5, i) for i, s in enumerate(s5)]
+    order = rng.permutation(len(items))
+    items = [items[k] for k in order]
+    rc, ln, nodes = B.solve_mixed_raw([it[0] for it in items])
+    assert rc == B.OK, B.strerror(rc)
+    for k, (s, want, i) in enumerate(items):
+        assert ln[k] == want.length[i] and (nodes[k] == want.nodes[i]).all(), k
+
+
+def test_plain_mode_is_15_puzzle_only(B):
+    from paper_1705_02843_amd import instances as I
+    B.set_option("mode", 0)
+    s3, _ = I.c4_mixed(n3=4, n4=1, n5=1)[3]
+    rc, _, _ = B.solve_raw(s3, 3)
+    assert rc == B.EINVAL
+
+
+def test_ring_too_small_for_5x5(B):
+    B.set_option("lds_stack_capacity", 256)
+    s = five_by_five_states(4)[:4]
+    rc, _, _ = B.solve_raw(np.stack(s), 5)
+    assert rc == B.EINVAL
