@@ -1,7 +1,8 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the gfx950 Block-Parallel IDA* path.
 
-One step = one full ``bpida_solve_device`` call over the workload's batch
+One step = one full ``bpida_solve_device`` call (``bpida_solve_mixed_device``
+for the mixed-width workload) over the workload's batch
 (ingest, root split, every f-limit of every instance with its search launch
 and reduction, outputs), with the start states already resident in HBM.
 
@@ -42,7 +43,11 @@ WORKLOADS = {
     "c1_walk40": ("64 15-puzzle states from seeded 40-move non-backtracking walks", 4),
     "c3_uneven": ("4096 15-puzzle states from seeded non-backtracking walks of length U{20..300}, "
                   "Manhattan <= 38, all-optimal-solutions final limit", 4),
+    "c4_mixed": ("2048 3x3 (walks U{20..300}) + 2048 4x4 (walks U{20..300}, Manhattan <= 38) + "
+                 "256 5x5 (60-move walks) states in one launch, all-optimal-solutions final limit", 0),
 }
+# the mixed workload's stored oracle results, one file per width (launch order)
+MIXED_PARTS = (("c4_mixed_w3", 3), ("c4_mixed_w4", 4), ("c4_mixed_w5", 5))
 MODES = {"plain": 0, "batched": 1}
 
 
@@ -55,44 +60,59 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def make_states(name):
+def make_parts(name):
+    """[(golden file name, states [n, w*w], width)] in launch order."""
     from paper_1705_02843_amd import instances
-    return getattr(instances, name)()[0]
+    if name == "c4_mixed":
+        d = instances.c4_mixed()
+        return [(g, d[w][0], w) for g, w in MIXED_PARTS]
+    return [(name, getattr(instances, name)()[0], WORKLOADS[name][1])]
 
 
-def golden_total(name):
-    path = os.path.join(ROOT, "tests", "golden", name + ".json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        return int(json.load(f)["total_nodes"])
+def golden_total(parts):
+    tot = 0
+    for g, _, _ in parts:
+        path = os.path.join(ROOT, "tests", "golden", g + ".json")
+        if not os.path.exists(path):
+            return None
+        with open(path) as f:
+            tot += int(json.load(f)["total_nodes"])
+    return tot
 
 
-def cpu_baseline(name, states, budget_nodes, nthreads):
-    """The oracle, untouched, on a bounded sample: instances taken in order,
-    skipping any whose stored node total alone exceeds a thread's share, until
-    the sample holds about ``budget_nodes`` nodes."""
+def cpu_baseline(parts, budget_nodes, nthreads):
+    """The oracle, untouched, on a bounded sample: from each part (width) of
+    the workload, instances taken in order, skipping any whose stored node
+    total alone exceeds a thread's share, until the part's sample holds about
+    its share of ``budget_nodes`` (in proportion to its node total)."""
     from oracle import oracle
-    path = os.path.join(ROOT, "tests", "golden", name + ".json")
-    with open(path) as f:
-        per = [sum(r["nodes"]) for r in json.load(f)["instances"]]
-    share = budget_nodes / max(1, nthreads) * 2
-    pick, tot = [], 0
-    for i, n in enumerate(per):
-        if n > share:
-            continue
-        pick.append(i)
-        tot += n
-        if tot >= budget_nodes:
-            break
-    t0 = time.perf_counter()
-    r = oracle.solve(states[pick], 4, nthreads=nthreads)
-    dt = time.perf_counter() - t0
-    assert r.rc == 0
-    return {"value": round(r.total_nodes / dt, 1), "unit": "nodes/s", "cores": nthreads,
+    per_part = []
+    for g, _, _ in parts:
+        with open(os.path.join(ROOT, "tests", "golden", g + ".json")) as f:
+            per_part.append([sum(r["nodes"]) for r in json.load(f)["instances"]])
+    grand = sum(sum(p) for p in per_part)
+    nodes = secs = count = 0
+    for (g, states, w), per in zip(parts, per_part):
+        budget = budget_nodes * sum(per) / grand
+        share = max(budget / max(1, nthreads) * 2, min(per))
+        pick, tot = [], 0
+        for i, n in enumerate(per):
+            if n > share:
+                continue
+            pick.append(i)
+            tot += n
+            if tot >= budget:
+                break
+        t0 = time.perf_counter()
+        r = oracle.solve(states[pick], w, nthreads=nthreads)
+        secs += time.perf_counter() - t0
+        assert r.rc == 0
+        nodes += r.total_nodes
+        count += len(pick)
+    return {"value": round(nodes / secs, 1), "unit": "nodes/s", "cores": nthreads,
             "kind": "oracle",
             "sample": "%d of the workload's instances (%d nodes, %.1f s wall, %d threads)" % (
-                len(pick), r.total_nodes, dt, nthreads)}
+                count, nodes, secs, nthreads)}
 
 
 def load_traffic(src_hash, mode, workload):
@@ -141,8 +161,17 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     desc, width = WORKLOADS[args.workload]
-    states = make_states(args.workload)
-    n = states.shape[0]
+    parts = make_parts(args.workload)
+    widths = None
+    if width == 0:  # mixed widths: bytes back to back, widths on the host
+        widths = np.concatenate([np.full(p[1].shape[0], p[2], np.int32) for p in parts])
+        states = np.concatenate([p[1].reshape(-1) for p in parts])
+        n = widths.shape[0]
+        if args.mode != "batched":
+            raise SystemExit("bench.py: the mixed-width workload runs in batched mode only")
+    else:
+        states = parts[0][1]
+        n = states.shape[0]
     tuned = None
     if not args.untuned:
         from paper_1705_02843_amd import autotune
@@ -169,7 +198,10 @@ def main():
                 bpida.set_option(k, -1 if k != "max_workgroups" else 0)
 
         def step():
-            rc = bpida.solve_device(d_states, d_len, d_nodes, width=width, stream=stream)
+            if widths is not None:
+                rc = bpida.solve_mixed_device(d_states, widths, d_len, d_nodes, stream=stream)
+            else:
+                rc = bpida.solve_device(d_states, d_len, d_nodes, width=width, stream=stream)
             if rc != bpida.OK:
                 raise bpida.BpidaError(rc, "bpida_solve_device")
 
@@ -191,7 +223,7 @@ def main():
         assert (d_len.cpu().numpy() >= 0).all()
         return dt, nodes_step, acc
 
-    expect = golden_total(args.workload)
+    expect = golden_total(parts)
     dt, nodes_per_step, acc = run_mode(args.mode, args.steps, args.warmup)
     search_nodes, search_us, launches = acc["search_nodes"], acc["search_us"], acc["launches"]
     rounds = acc["rounds"]
@@ -266,7 +298,7 @@ def main():
         bpida.set_option("mode", MODES[args.mode])
     if not args.no_cpu_baseline:
         nthreads = min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(args.workload, states, args.cpu_budget_nodes, nthreads)
+        out["cpu_baseline"] = cpu_baseline(parts, args.cpu_budget_nodes, nthreads)
     print(json.dumps(out), flush=True)
 
 

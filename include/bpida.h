@@ -92,6 +92,17 @@ int bpida_solve_mixed(const uint8_t *states, const int32_t *widths, int32_t n_in
                       int32_t *out_len, uint64_t *out_nodes_per_threshold);
 
 /*
+ * As bpida_solve_mixed with the states and outputs in device memory of the
+ * current device (d_states: the instances' bytes back to back; d_len, d_nodes
+ * as in bpida_solve_device) and the widths in host memory (n int32 in 3..5;
+ * the host lays out the split trees from them).  Work is ordered on
+ * `hip_stream` (NULL = the null stream); returns after the results are in
+ * d_len and d_nodes, with the first failing status in instance order.
+ */
+int bpida_solve_mixed_device(const uint8_t *d_states, const int32_t *widths, int32_t n_instances,
+                             int32_t *d_len, uint64_t *d_nodes, void *hip_stream);
+
+/*
  * As bpida_solve, with every buffer in device memory of the current device:
  * d_states (n * width * width bytes), d_len (n int32), d_nodes
  * (n * BPIDA_MAX_THRESHOLDS uint64).  Validation runs on the device; the
@@ -214,7 +225,8 @@ int64_t bpida_get_option(const char *key);
  *          or spilled chunks x 64)
  *   out[3] search-kernel launches
  *   out[4] search-kernel time in microseconds (device events, summed)
- *   out[5] plain mode: largest per-workgroup spill stack seen, in entries
+ *   out[5] plain mode: largest per-workgroup spill stack seen, in entries;
+ *          batched mode: most chunks queued at once (seen at a push)
  *   out[6] batched mode: chunks pushed to the work queue (seeds excluded)
  *   out[7] batched mode: chunks popped from the work queue
  *   out[8..10] batched mode: microseconds summed over workgroups spent
@@ -224,6 +236,7 @@ int64_t bpida_get_option(const char *key);
  *   out[13] batched mode: error bits (1 queue full while seeding, 2 entries
  *          dropped, 4 idle watchdog, 8 deadline, 16 queue ring full,
  *          256 split check)
+ *   out[14] batched mode: work-queue slots (chunks of 64 entries)
  * n = number of slots to fill (<= 16).  Returns BPIDA_OK or BPIDA_EINVAL.
  */
 int bpida_last_stats(uint64_t *out, int32_t n);

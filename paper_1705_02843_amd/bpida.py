@@ -17,7 +17,7 @@ OK, EINVAL, EUNSOLVABLE, ELIMIT, ENOMEM, EDEVICE, EINTERNAL, EAGAIN = 0, -1, -2,
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbpida.so")
 
-EXPORTS = ("bpida_solve", "bpida_solve_mixed", "bpida_solve_device", "bpida_solve_device_async", "bpida_set_option",
+EXPORTS = ("bpida_solve", "bpida_solve_mixed", "bpida_solve_mixed_device", "bpida_solve_device", "bpida_solve_device_async", "bpida_set_option",
            "bpida_get_option", "bpida_last_stats", "bpida_strerror", "bpida_server_start",
            "bpida_server_submit", "bpida_server_poll", "bpida_server_stop")
 
@@ -40,6 +40,9 @@ def _load() -> ctypes.CDLL:
     lib.bpida_solve_mixed.argtypes = [P(ctypes.c_uint8), P(ctypes.c_int32), ctypes.c_int32,
                                       P(ctypes.c_int32), P(ctypes.c_uint64)]
     lib.bpida_solve_mixed.restype = ctypes.c_int
+    lib.bpida_solve_mixed_device.argtypes = [ctypes.c_void_p, P(ctypes.c_int32), ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.bpida_solve_mixed_device.restype = ctypes.c_int
     lib.bpida_solve_device.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.bpida_solve_device.restype = ctypes.c_int
@@ -92,7 +95,7 @@ def last_stats() -> dict:
         raise BpidaError(rc, "last_stats")
     keys = ("rounds", "search_nodes", "spilled", "launches", "search_us", "spill_high_water",
             "chunks_pushed", "chunks_popped", "wg_us_search", "wg_us_queue", "wg_us_idle",
-            "donations_voluntary", "grid", "error_bits")
+            "donations_voluntary", "grid", "error_bits", "queue_slots")
     return {k: int(out[i]) for i, k in enumerate(keys)}
 
 
@@ -151,6 +154,27 @@ def solve_device(d_states, d_len, d_nodes, width: int = 4, stream=None) -> int:
                                       ctypes.c_void_p(d_len.data_ptr()),
                                       ctypes.c_void_p(d_nodes.data_ptr()),
                                       ctypes.c_void_p(s.cuda_stream)))
+
+
+def solve_mixed_device(d_states, widths, d_len, d_nodes, stream=None) -> int:
+    """Mixed-width batch on torch tensors: ``d_states`` uint8 on the device,
+    the instances' bytes back to back; ``widths`` host int32 [n] (numpy).
+    Outputs as in ``solve_device``.  Returns the status code."""
+    import torch  # device buffers and streams only
+
+    w = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
+    n = int(w.shape[0])
+    assert d_states.is_cuda and d_states.dtype == torch.uint8 and d_states.is_contiguous()
+    assert d_states.numel() == int((w.astype(np.int64) ** 2).sum())
+    assert d_len.is_cuda and d_len.dtype == torch.int32 and d_len.numel() >= n
+    assert d_nodes.is_cuda and d_nodes.dtype in (torch.int64, torch.uint64)
+    assert d_nodes.is_contiguous() and d_nodes.numel() >= n * MAX_THRESHOLDS
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(lib.bpida_solve_mixed_device(ctypes.c_void_p(d_states.data_ptr()),
+                                            w.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n,
+                                            ctypes.c_void_p(d_len.data_ptr()),
+                                            ctypes.c_void_p(d_nodes.data_ptr()),
+                                            ctypes.c_void_p(s.cuda_stream)))
 
 
 def solve_device_async(d_states, d_len, d_nodes, d_status, width: int = 4, stream=None) -> int:

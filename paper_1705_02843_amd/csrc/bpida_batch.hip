@@ -64,6 +64,8 @@ __device__ bool q_push(const BatchArgs& A, uint64_t tile, uint64_t hi, uint16_t 
   int ok = 0;
   if (lane == 0) {
     pos = __hip_atomic_fetch_add(&q->tail, (uint64_t)1, __ATOMIC_RELAXED, AGENT);
+    const uint64_t h = ld_relaxed(&q->head);
+    if (pos + 1 > h) __hip_atomic_fetch_max(&q->qmax, pos + 1 - h, __ATOMIC_RELAXED, AGENT);
     for (int k = 0; k < kPushSpin; ++k) {
       if (ld_relaxed(&A.seq[pos & mask]) == pos) {
         ok = 1;

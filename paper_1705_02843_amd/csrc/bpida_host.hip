@@ -78,6 +78,7 @@ struct Workspace {
   int num_cu = 0;
   int wall_khz = 100000;
   bool arch_ok = false;
+  uint64_t qcap = 0;  // queue slots of the last batched launch
   DevBuf inst, tree, tree_off, hist, goal_g, err, cursor, part, spill_t, spill_m, res;
   DevBuf qctl, qseq, qslots, istate, root_off, nroots, status, walks;
   // non-backtracking walk counts per width (3, 4, 5), start cell and length
@@ -351,6 +352,7 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
   // value travels back to the host before the persistent launch: the whole
   // solve is one stream-ordered sequence of kernels.
   int64_t tree_nodes = 0, seed_chunks = 0, stride = 0;
+  bool any5 = width == 5;
   if (!h_widths) {
     int64_t mr = 0;
     tree_size(W, width, D, &stride, &mr);
@@ -363,6 +365,7 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
     for (int i = 0; i < n; ++i) {
       const int w = h_widths[i];
       if (w < 3 || w > 5 || !ring_fits(w, cap)) return BPIDA_EINVAL;
+      any5 = any5 || w == 5;
       int64_t sw = 0, mr = 0;
       tree_size(W, w, D, &sw, &mr);
       toff[i] = tree_nodes;
@@ -396,9 +399,15 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
   int64_t grid = (int64_t)per_cu * W.num_cu;
   if (O.max_workgroups > 0) grid = std::min<int64_t>(grid, O.max_workgroups);
   uint64_t qcap = 64;
+  // Default size: the seeds plus, per workgroup, room for the chunks its
+  // ring overflows into.  A 5x5 subtree's stack runs deeper and its ring
+  // holds half as many entries, so it spills several times more (measured
+  // peaks: about 6 chunks per workgroup for 4x4 batches, 36 for 5x5).
+  const int64_t per_wg = any5 ? 64 : 16;
   const uint64_t want = O.queue_capacity > 0 ? (uint64_t)O.queue_capacity
-                                              : (uint64_t)(seed_chunks + grid * 16 + 1024);
+                                              : (uint64_t)(seed_chunks + grid * per_wg + 1024);
   while (qcap < want) qcap <<= 1;
+  W.qcap = qcap;
   HIPCHK(W.qctl.ensure(sizeof(QueueCtl)));
   HIPCHK(W.qseq.ensure(sizeof(uint64_t) * qcap));
   HIPCHK(W.qslots.ensure(sizeof(QChunk) * qcap));
@@ -474,8 +483,10 @@ int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_node
   stats[9] = qc.t_queue / (uint64_t)std::max(1, W.wall_khz / 1000);
   stats[10] = qc.t_idle / (uint64_t)std::max(1, W.wall_khz / 1000);
   stats[11] = qc.voluntary;
+  stats[5] = qc.qmax;
   stats[12] = (uint64_t)grid;
   stats[13] = (uint64_t)(uint32_t)qc.err | ((uint64_t)(split_err != 0) << 8);
+  stats[14] = W.qcap;
   memcpy(g_stats, stats, sizeof stats);
   int rc = BPIDA_OK;
   for (int i = 0; i < n && rc == BPIDA_OK; ++i)
@@ -559,6 +570,27 @@ extern "C" int bpida_solve_mixed(const uint8_t* states, const int32_t* widths, i
         hipStreamSynchronize(st) != hipSuccess)
       return BPIDA_EDEVICE;
     return rc;
+  } catch (const std::bad_alloc&) {
+    return BPIDA_ENOMEM;
+  } catch (...) {
+    return BPIDA_EINTERNAL;
+  }
+}
+
+extern "C" int bpida_solve_mixed_device(const uint8_t* d_states, const int32_t* widths,
+                                        int32_t n_instances, int32_t* d_len, uint64_t* d_nodes,
+                                        void* hip_stream) {
+  try {
+    if (!d_states || !widths || !d_len || !d_nodes || n_instances < 0) return BPIDA_EINVAL;
+    for (int32_t i = 0; i < n_instances; ++i)
+      if (widths[i] < BPIDA_MIN_WIDTH || widths[i] > BPIDA_MAX_WIDTH) return BPIDA_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Options O = g_opt;
+    O.mode = kModeBatched;
+    if (n_instances == 0) return BPIDA_OK;
+    int rc = ensure_device();
+    if (rc != BPIDA_OK) return rc;
+    return run_batched(d_states, n_instances, d_len, d_nodes, (hipStream_t)hip_stream, O, 0, widths);
   } catch (const std::bad_alloc&) {
     return BPIDA_ENOMEM;
   } catch (...) {

@@ -162,6 +162,7 @@ struct QueueCtl {
   uint64_t searched, pushes, pops;
   uint64_t t_work, t_queue, t_idle;  // wall-clock ticks summed over workgroups
   uint64_t voluntary;                // donations made because workgroups idled
+  uint64_t qmax;                     // most chunks queued at once (seen at a push)
 };
 
 // ---------------------------------------------------------------------------

@@ -28,6 +28,10 @@ SPECS = {
     "c2_md30_38": (lambda: instances.c2_md30_38(), 4),
     "c3_uneven_first512": (lambda: tuple(x[:512] for x in instances.c3_uneven()), 4),
     "c3_uneven": (lambda: instances.c3_uneven(), 4),
+    # the mixed-width workload, one file per width (launch order 3, 4, 5)
+    "c4_mixed_w3": (lambda: instances.c4_mixed()[3], 3),
+    "c4_mixed_w4": (lambda: instances.c4_mixed()[4], 4),
+    "c4_mixed_w5": (lambda: instances.c4_mixed()[5], 5),
 }
 
 

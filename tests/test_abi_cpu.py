@@ -51,6 +51,18 @@ def test_argument_errors_before_device_work(B):
     assert B.lib.bpida_solve_device(None, 1, 4, None, None, None) == B.EINVAL
     assert B.lib.bpida_solve_device(ctypes.c_void_p(8), 0, 4, ctypes.c_void_p(8),
                                     ctypes.c_void_p(8), None) == B.OK
+    wd = np.array([4], np.int32)
+    wp = wd.ctypes.data_as(P(ctypes.c_int32))
+    bad = np.array([6], np.int32).ctypes.data_as(P(ctypes.c_int32))
+    assert B.lib.bpida_solve_mixed(sp, None, 1, lp, npp) == B.EINVAL
+    assert B.lib.bpida_solve_mixed(sp, bad, 1, lp, npp) == B.EINVAL
+    assert B.lib.bpida_solve_mixed(sp, wp, 0, lp, npp) == B.OK
+    assert B.lib.bpida_solve_mixed_device(None, wp, 1, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                                          None) == B.EINVAL
+    assert B.lib.bpida_solve_mixed_device(ctypes.c_void_p(8), bad, 1, ctypes.c_void_p(8),
+                                          ctypes.c_void_p(8), None) == B.EINVAL
+    assert B.lib.bpida_solve_mixed_device(ctypes.c_void_p(8), wp, 0, ctypes.c_void_p(8),
+                                          ctypes.c_void_p(8), None) == B.OK
     assert (ln == 0).all() and (nd == 0).all()  # outputs untouched
 
 

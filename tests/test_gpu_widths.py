@@ -105,3 +105,52 @@ def test_ring_too_small_for_5x5(B):
     s = five_by_five_states(4)[:4]
     rc, _, _ = B.solve_raw(np.stack(s), 5)
     assert rc == B.EINVAL
+
+
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def test_c4_mixed_one_launch_exact_and_same_as_alone(B):
+    """The mixed-width workload (2048 3x3 + 2048 4x4 + 256 5x5) in one
+    launch: every instance equal to its width's batch run alone, and exact
+    against the stored oracle results of every width that has them."""
+    import torch
+    from paper_1705_02843_amd import instances as I
+    print("case: c4 mixed workload, 4352 states, one launch", flush=True)
+    d = I.c4_mixed()
+    parts = [(3, d[3][0]), (4, d[4][0]), (5, d[5][0])]
+    widths = np.concatenate([np.full(s.shape[0], w, np.int32) for w, s in parts])
+    flat = np.concatenate([s.reshape(-1) for _, s in parts])
+    n = widths.shape[0]
+    d_states = torch.from_numpy(flat).cuda()
+    d_len = torch.empty(n, dtype=torch.int32, device="cuda")
+    d_nodes = torch.empty((n, B.MAX_THRESHOLDS), dtype=torch.int64, device="cuda")
+    rc = B.solve_mixed_device(d_states, widths, d_len, d_nodes)
+    assert rc == B.OK, B.strerror(rc)
+    torch.cuda.synchronize()
+    ln = d_len.cpu().numpy()
+    nodes = d_nodes.cpu().numpy().view(np.uint64)
+    off = 0
+    for w, s in parts:
+        k = s.shape[0]
+        print("case: c4 width %d alone" % w, flush=True)
+        rc, aln, anodes = B.solve_raw(s, w)
+        assert rc == B.OK, B.strerror(rc)
+        assert (aln == ln[off:off + k]).all() and (anodes == nodes[off:off + k]).all(), w
+        g = _golden("c4_mixed_w%d" % w)
+        if g is not None:
+            for i, r in enumerate(g["instances"]):
+                m = len(r["nodes"])
+                assert ln[off + i] == r["length"], (w, i)
+                assert list(nodes[off + i, :m]) == r["nodes"] and not nodes[off + i, m:].any(), (w, i)
+        else:
+            h0 = np.array([I.manhattan_filter_value(x, w) for x in s])
+            assert (ln[off:off + k] >= h0).all() and ((ln[off:off + k] - h0) % 2 == 0).all()
+        off += k
