@@ -516,9 +516,9 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   constexpr int kGrow = NPL == 16 ? 32 : 3 * 64;
   const LaneMap M = make_lane_map(lane);
   int smax = INT_MIN;
-  int top = cnt, bot = 0;
+  uint32_t top = (uint32_t)cnt, bot = 0;  // unsigned: they wrap, top - bot stays small
   while (top != bot) {
-    int avail = top - bot;
+    int avail = (int)(top - bot);
     ++tick;
     if ((tick & 1023u) == 0 && wall_clock64() > deadline) {
       if (lane == 0) atomicOr(&q->err, 8);
@@ -526,7 +526,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
     }
     if (avail + kGrow > CAP) {
       // LDS would overflow: move the 64 oldest entries to the queue
-      const int p = (bot + lane) & (CAP - 1);
+      const uint32_t p = (bot + (uint32_t)lane) & (CAP - 1);
       const S t = st[p];
       const uint16_t m = sm[p];
       WAVE_SYNC();
@@ -549,8 +549,8 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
       if (wave_bcast(want)) {
         const int w = min(avail, 128) & ~1;
         const int h = w >> 1;
-        const int pg = (bot + 2 * lane) & (CAP - 1);
-        const int pk = (bot + 2 * lane + 1) & (CAP - 1);
+        const uint32_t pg = (bot + 2u * (uint32_t)lane) & (CAP - 1);
+        const uint32_t pk = (bot + 2u * (uint32_t)lane + 1u) & (CAP - 1);
         const S tg = st[pg], tk = st[pk];
         const uint16_t mg = sm[pg], mk = sm[pk];
         WAVE_SYNC();
@@ -560,12 +560,12 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
           wc.pushes += 1;
           wc.voluntary += 1;
           if (lane < h) {
-            const int pn = (bot + h + lane) & (CAP - 1);
+            const uint32_t pn = (bot + (uint32_t)(h + lane)) & (CAP - 1);
             st[pn] = tk;
             sm[pn] = mk;
           }
           WAVE_SYNC();
-          bot += h;
+          bot += (uint32_t)h;
           avail -= h;
         } else if (lane == 0) {
           __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
@@ -862,7 +862,8 @@ __device__ void split_impl(const InstW& I, int depth, const int32_t* walks, Node
     const int64_t next = lvl + cnt;
     for (int k = threadIdx.x; k < cnt; k += kSplitThreadsW) {
       const NodeW nd = base[lvl + k];
-      const S s = (S)nd.lo | (W == 5 ? ((S)nd.hi << 64) : (S)0);
+      S s = (S)nd.lo;
+      if constexpr (W == 5) s |= (S)nd.hi << 64;
       const uint32_t b = nd.meta & 31u, fb = (nd.meta >> 5) & 7u;
       const int g = (int)((nd.meta >> 8) & 255u), h = (int)((nd.meta >> 16) & 255u);
       atomicAdd(&h_lds[min(g + h, kHistBins - 1)], 1u);

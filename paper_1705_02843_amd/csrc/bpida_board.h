@@ -49,6 +49,52 @@ struct Board {
     return tab;
   }
 
+  // Index parts of the blank's cell b used by up(): for width 4 the row and
+  // 4 * column, else the row and the column.
+  static constexpr __host__ __device__ uint32_t row_part(uint32_t b) { return W == 4 ? b >> 2 : b / W; }
+  static constexpr __host__ __device__ uint32_t col_part(uint32_t b) {
+    return W == 4 ? (b & 3u) << 2 : b % W;
+  }
+
+  // 1 iff move a takes the tile it slides away from the tile's goal cell.
+  // x holds the tile (its number t) in its low BITS bits; higher bits are
+  // ignored.  The tile sits at the blank's neighbour and only one of its
+  // coordinates changes; the table bit for (goal coordinate, neighbour
+  // coordinate) is read with the neighbour's coordinate taken as the
+  // blank's + step, i.e. from a shifted table.  For width 4, ct * 4 = t & 12
+  // (rows) and, on a transposed table, the index is 4 * cb | ct with
+  // ct = t & 3 (columns): one AND-OR per move.
+  template <int A>
+  static constexpr __host__ __device__ uint32_t up(uint32_t x, uint32_t rowp, uint32_t colp) {
+    constexpr bool vert = A == 0 || A == 3;
+    constexpr int step = (A == 0 || A == 1) ? -1 : 1;  // neighbour coordinate minus blank's
+    constexpr uint32_t tab = table(A);
+    if constexpr (W == 4) {
+      if constexpr (vert) {
+        constexpr uint32_t t2 = step < 0 ? (tab << 1) : (tab >> 1);
+        return (t2 >> ((x & 12u) | rowp)) & 1u;
+      } else {
+        constexpr uint32_t tt = transposed(tab);
+        constexpr uint32_t t2 = step < 0 ? (tt << 4) : (tt >> 4);
+        return (t2 >> ((x & 3u) | colp)) & 1u;
+      }
+    } else {
+      constexpr uint32_t t2 = step < 0 ? (tab << 1) : (tab >> 1);
+      const uint32_t t = x & MASK;
+      const uint32_t ct = vert ? t / W : t % W;
+      return (t2 >> ((ct * W + (vert ? rowp : colp)) & 31u)) & 1u;
+    }
+  }
+
+  // table(a) with its two coordinates swapped: bit (cn * W + ct).
+  static constexpr uint32_t transposed(uint32_t tab) {
+    uint32_t t = 0;
+    for (int ct = 0; ct < W; ++ct)
+      for (int cn = 0; cn < W; ++cn)
+        if ((tab >> (ct * W + cn)) & 1u) t |= 1u << (cn * W + ct);
+    return t;
+  }
+
   // Bit a set iff move a keeps a blank at cell b on the board.
   static __device__ __forceinline__ uint32_t legal(uint32_t b) {
     const uint32_t r = b / W, c = b - r * W;
@@ -56,75 +102,182 @@ struct Board {
   }
 };
 
+// Legal moves per blank cell, 4 bits per cell (bit a: move a keeps the
+// blank on the board), for boards of at most 16 cells.
+template <int W>
+constexpr uint64_t legal_table() {
+  uint64_t t = 0;
+  for (int p = 0; p < W * W && p < 16; ++p) {
+    const int r = p / W, c = p % W;
+    const uint64_t m = (r > 0 ? 1u : 0u) | (c > 0 ? 2u : 0u) | (c < W - 1 ? 4u : 0u) |
+                       (r < W - 1 ? 8u : 0u);
+    t |= m << (4 * p);
+  }
+  return t;
+}
+
+// Compile-time proof of the lookups against their definitions: for every
+// blank cell, tile and legal move, up() equals "the tile's Manhattan
+// distance to its goal cell grows", and legal_table equals the board edges.
+template <int W>
+constexpr bool check_lookups() {
+  using B = Board<W>;
+  for (int b = 0; b < W * W; ++b) {
+    const int r = b / W, c = b % W;
+    const bool lg[4] = {r > 0, c > 0, c < W - 1, r < W - 1};
+    const int dn[4] = {-W, -1, 1, W};
+    if (W * W <= 16) {
+      uint32_t m = 0;
+      for (int a = 0; a < 4; ++a) m |= lg[a] ? 1u << a : 0u;
+      if (((legal_table<W>() >> (4 * b)) & 15u) != m) return false;
+    }
+    for (int a = 0; a < 4; ++a) {
+      if (!lg[a]) continue;
+      const int n = b + dn[a];
+      for (int t = 1; t < W * W; ++t) {
+        const int gr = t / W, gc = t % W;
+        const int before = (gr > n / W ? gr - n / W : n / W - gr) + (gc > n % W ? gc - n % W : n % W - gc);
+        const int after = (gr > r ? gr - r : r - gr) + (gc > c ? gc - c : c - gc);
+        const uint32_t want = after > before ? 1u : 0u;
+        // garbage above the tile's bits must not matter
+        const uint32_t x = (uint32_t)t | (0xABCD00u << B::BITS);
+        uint32_t got = 0;
+        const uint32_t rp = B::row_part((uint32_t)b), cp = B::col_part((uint32_t)b);
+        if (a == 0) got = B::template up<0>(x, rp, cp);
+        if (a == 1) got = B::template up<1>(x, rp, cp);
+        if (a == 2) got = B::template up<2>(x, rp, cp);
+        if (a == 3) got = B::template up<3>(x, rp, cp);
+        if (got != want) return false;
+      }
+    }
+  }
+  return true;
+}
+static_assert(check_lookups<3>() && check_lookups<4>() && check_lookups<5>(),
+              "move tables disagree with the board");
+
+// 24-bit unsigned product kept in 32 bits (the operands are a tile number and
+// a constant below 2^20), so the compiler does not widen it to 64 bits.
+__device__ __forceinline__ uint32_t mul_u24(uint32_t k, uint32_t t) {
+  uint32_t r;
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(k), "v"(t));
+  return r;
+}
+
+// a * b + c on 24-bit signed a, b (one instruction; the compiler would
+// otherwise shift and subtract).
+__device__ __forceinline__ uint32_t mad_i24(uint32_t a, int b, uint32_t c) {
+  uint32_t r;
+  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
+
+// Hides a value's known bits from the optimiser (no instruction is emitted).
+// Used where the compiler would otherwise re-derive one condition in two
+// forms, or keep a shift-amount mask the hardware applies anyway.
+__device__ __forceinline__ uint32_t opaque(uint32_t v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
+// Per-node values shared by the four moves of a 64-node round.
+struct NodeCtx {
+  uint32_t b;      // blank cell
+  uint32_t shb;    // BITS * b
+  uint32_t rowi;   // vertical moves: the blank's row (table index part)
+  uint32_t coli;   // horizontal moves: the blank's column (x W for width 4)
+  uint32_t lmx;    // bit (A + 4 up): move A survives the f test
+  uint32_t mbase;  // slack << 8 | blank
+};
+
 // One move for every lane of a 64-node round (see bp_round64w).
 template <int W, int CAP, int A>
-__device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm, int& out,
-                                          const typename Board<W>::S s, uint32_t b, uint32_t rb,
-                                          uint32_t cb, uint32_t lm, int slack, uint32_t& anyup) {
+__device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm, uint32_t& out,
+                                          const typename Board<W>::S s, const NodeCtx& c,
+                                          uint32_t& upm) {
   using B = Board<W>;
   using S = typename B::S;
   constexpr int delta = A == 0 ? -W : A == 1 ? -1 : A == 2 ? 1 : W;
   constexpr bool vert = A == 0 || A == 3;
-  constexpr int step = (A == 0 || A == 1) ? -1 : 1;  // neighbour coordinate minus blank's
-  constexpr uint32_t tab = B::table(A);
-  // index (ct * W + cb) reads bit (ct * W + cb + step) of the table
-  constexpr uint32_t tab2 = step < 0 ? (tab << 1) : (tab >> 1);
   constexpr uint32_t K = vert ? ((1u << (B::BITS * W)) - 1u) : B::MASK;
-  const uint32_t n = b + (uint32_t)delta;  // wraps (and is unused) when illegal
-  const uint32_t sh_n = (B::BITS * n) & (8u * sizeof(S) - 1u);
-  const uint32_t t = (uint32_t)(s >> sh_n) & B::MASK;
-  const uint32_t ct = vert ? t / W : t % W;
-  const uint32_t up = (tab2 >> ((ct * W + (vert ? rb : cb)) & 31u)) & 1u;
-  const int slack2 = slack - (int)(up << 1);
-  const uint32_t legal = (lm >> A) & 1u;
-  anyup |= legal & up;
-  const bool keep = legal != 0u && slack2 >= 0;
-  // successor: t moves from n to b, i.e. the packed word changes by
-  // t * (base^b - base^n) = +/- (K * t) << (BITS * min(b, n))
-  const S d = (S)(K * t) << (A < 2 ? sh_n : B::BITS * b);
-  const S cs = A < 2 ? s + d : s - d;
-  // stack meta: n | (3 - A) << 5 | slack2 << 8 (n = b + delta on a legal move)
-  const uint32_t cm = ((uint32_t)slack2 << 8) + b + (uint32_t)(delta + ((3 - A) << 5));
-  const uint64_t km = __builtin_amdgcn_ballot_w64(keep);
-  if (keep) {
-    const uint32_t off = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
-                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
-    const uint32_t p = ((uint32_t)out + off) & (uint32_t)(CAP - 1);
-    st[p] = cs;
-    sm[p] = (uint16_t)cm;
+  // shift to the neighbour's cell; it wraps (and the tile is unused) when
+  // the move is illegal
+  const uint32_t sh_n = (c.shb + (uint32_t)(B::BITS * delta)) & (8u * sizeof(S) - 1u);
+  const uint32_t x = (uint32_t)(s >> sh_n);  // tile t in the low BITS bits
+  const uint32_t up = B::template up<A>(x, c.rowi, c.coli);
+  upm |= up << A;
+  const uint32_t kb = opaque((c.lmx >> (A + 4 * up)) & 1u);
+  const uint64_t km = __builtin_amdgcn_uicmp(kb, 0u, 33);  // lanes with kb != 0
+  if (kb != 0u) {
+    // successor: t moves from n to b, i.e. the packed word changes by
+    // t * (base^b - base^n) = +/- (K * t) << (BITS * min(b, n))
+    // (on a legal move the neighbour's shift is in range without the mask)
+    uint32_t kt;
+    if constexpr (K < (1u << 24)) kt = mul_u24(K, x & B::MASK);
+    else kt = K * (x & B::MASK);  // 5x5 rows: K = 2^25 - 1
+    const S d = (S)kt << (A < 2 ? c.shb + (uint32_t)(B::BITS * delta) : c.shb);
+    const S cs = A < 2 ? s + d : s - d;
+    // stack meta: n | (3 - A) << 5 | (slack - 2 up) << 8
+    const uint32_t cm = mad_i24(up, -512, c.mbase) + (uint32_t)(delta + ((3 - A) << 5));
+    const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+    // byte offsets into the ring: entry (out + r) mod CAP
+    constexpr uint32_t LS = sizeof(S) == 8 ? 3 : 4;
+    const uint32_t pst = ((r + out) << LS) & ((uint32_t)(CAP << LS) - 1u);
+    *(S*)((char*)st + pst) = cs;
+    *(uint16_t*)((char*)sm + (pst >> (LS - 1))) = (uint16_t)cm;
   }
-  out += __popcll(km);
+  out += (uint32_t)__popcll(km);
 }
 
 // One BPDFS round with one popped node per lane, for any board width: pops
 // kp = min(64, top - bot) nodes, tests them for the goal and pushes every
 // legal, non-undoing child with f <= limit.  The caller guarantees
-// top - bot + 3*kp <= CAP.  `smax` tracks the largest slack of a pruned
+// top - bot + 3*kp <= CAP.  Ring positions are unsigned and wrap.  `smax` tracks the largest slack of a pruned
 // child (always slack - 2 of a node whose tile moves away from its goal).
 template <int W, int CAP>
-__device__ __forceinline__ int bp_round64w(typename Board<W>::S* st, uint16_t* sm, int top, int kp,
+__device__ __forceinline__ uint32_t bp_round64w(typename Board<W>::S* st, uint16_t* sm, uint32_t top, int kp,
                                            int& goals, int& smax) {
   using B = Board<W>;
   using S = typename B::S;
   const int lane = threadIdx.x;
-  const int base = top - kp;
-  const int idx = (base + lane) & (CAP - 1);
-  const S s = st[idx];
-  const uint32_t m = sm[idx];
+  const uint32_t base = top - (uint32_t)kp;
+  constexpr uint32_t LS = sizeof(S) == 8 ? 3 : 4;
+  const uint32_t pst = ((base + (uint32_t)lane) << LS) & ((uint32_t)(CAP << LS) - 1u);
+  const S s = *(const S*)((const char*)st + pst);
+  const uint32_t m = *(const uint16_t*)((const char*)sm + (pst >> (LS - 1)));
   const bool act = lane < kp;
-  goals += __popcll(__builtin_amdgcn_ballot_w64(act && s == B::goal()));
-  const uint32_t b = m & 31u;
+  const uint64_t actm = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
+  uint64_t gm;
+  if constexpr (sizeof(S) == 8) gm = __builtin_amdgcn_uicmpl((uint64_t)s, (uint64_t)B::goal(), 32);
+  else gm = __builtin_amdgcn_ballot_w64(s == B::goal());
+  goals += __popcll(gm & actm);
+  NodeCtx c;
+  c.b = m & 31u;
+  c.shb = opaque(B::BITS * c.b);
   const uint32_t fb = (m >> 5) & 7u;
-  const int slack = (int)(m >> 8);
-  const uint32_t lm = act ? B::legal(b) & ~(1u << fb) : 0u;
-  const uint32_t rb = b / W, cb = b - rb * W;
-  uint32_t anyup = 0;
-  int out = base;
-  bp_move_w<W, CAP, 0>(st, sm, out, s, b, rb, cb, lm, slack, anyup);
-  bp_move_w<W, CAP, 1>(st, sm, out, s, b, rb, cb, lm, slack, anyup);
-  bp_move_w<W, CAP, 2>(st, sm, out, s, b, rb, cb, lm, slack, anyup);
-  bp_move_w<W, CAP, 3>(st, sm, out, s, b, rb, cb, lm, slack, anyup);
-  if (anyup != 0u && slack < 2) smax = max(smax, slack - 2);
+  uint32_t lm;
+  if constexpr (W * W <= 16) {
+    lm = (uint32_t)(legal_table<W>() >> (4u * c.b)) & ~(1u << fb) & 15u;
+  } else {
+    lm = B::legal(c.b) & ~(1u << fb);
+  }
+  lm = act ? lm : 0u;
+  // moves that survive: any legal one if its tile approaches its goal, and
+  // only with slack >= 2 if it moves away
+  const bool roomy = m >= (2u << 8);
+  c.lmx = ((roomy ? lm : 0u) << 4) | lm;
+  c.rowi = B::row_part(c.b);
+  c.coli = B::col_part(c.b);
+  c.mbase = (m & 0xFF00u) | c.b;
+  uint32_t upm = 0;
+  uint32_t out = base;
+  bp_move_w<W, CAP, 0>(st, sm, out, s, c, upm);
+  bp_move_w<W, CAP, 1>(st, sm, out, s, c, upm);
+  bp_move_w<W, CAP, 2>(st, sm, out, s, c, upm);
+  bp_move_w<W, CAP, 3>(st, sm, out, s, c, upm);
+  // a pruned child exists iff a legal move goes away from the goal at slack < 2
+  if (!roomy && (upm & lm) != 0u) smax = max(smax, (int)(m >> 8) - 2);
   WAVE_SYNC();
   return out;
 }

@@ -230,13 +230,14 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
       sm[0] = (uint16_t)((R.meta & 0xFFu) | ((uint32_t)(limit - (int)R.f) << 8));
     }
     WAVE_SYNC();
-    int top = 1, bot = 0, sp = 0;
+    uint32_t top = 1, bot = 0;  // unsigned ring positions: they wrap
+    int sp = 0;
     for (;;) {
-      int avail = top - bot;
+      int avail = (int)(top - bot);
       if (avail < 16 && sp > 0 && avail + kChunk <= CAP) {
         sp -= kChunk;
         bot -= kChunk;
-        const int p = (bot + lane) & (CAP - 1);
+        const uint32_t p = (bot + (uint32_t)lane) & (CAP - 1);
         st[p] = sp_t[sp + lane];
         sm[p] = sp_m[sp + lane];
         avail += kChunk;
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
         if (sp + kChunk > spill_cap) {
           err = 1;  // entries are dropped; the host reports BPIDA_ENOMEM
         } else {
-          const int p = (bot + lane) & (CAP - 1);
+          const uint32_t p = (bot + (uint32_t)lane) & (CAP - 1);
           sp_t[sp + lane] = st[p];
           sp_m[sp + lane] = sm[p];
           sp += kChunk;

@@ -52,11 +52,12 @@ __device__ __forceinline__ uint16_t stack_meta(int blank, int forbid, int slack)
 // the goal, generates all legal non-undoing children and pushes those with
 // f <= limit at the top (atomicPut: ballot + mbcnt prefix, one wave-wide
 // step).  Returns the new top.  The caller guarantees top - bot + 2*kp <= CAP.
+// Ring positions are unsigned and wrap; only top - bot is ever compared.
 template <int CAP>
-__device__ __forceinline__ int bp_round(uint64_t* st, uint16_t* sm, int top, int kp, int limit,
-                                        const LaneMap& M, int& goals, int& fmin) {
-  const int base = top - kp;
-  const int idx = (base + M.e) & (CAP - 1);
+__device__ __forceinline__ uint32_t bp_round(uint64_t* st, uint16_t* sm, uint32_t top, int kp, int limit,
+                                             const LaneMap& M, int& goals, int& fmin) {
+  const uint32_t base = top - (uint32_t)kp;
+  const uint32_t idx = (base + (uint32_t)M.e) & (CAP - 1);
   const uint64_t s = st[idx];
   const uint32_t m = sm[idx];
   const bool act = M.e < kp;
@@ -79,15 +80,15 @@ __device__ __forceinline__ int bp_round(uint64_t* st, uint16_t* sm, int top, int
   const uint64_t cs = s + ((uint64_t)t << (4 * b)) - ((uint64_t)t << (4 * n));
   const uint32_t cm = (uint32_t)n | ((uint32_t)(3 - M.a) << 5) | ((uint32_t)slack2 << 8);
   const uint64_t km = __ballot(keep);
-  const int off = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
-                                            __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+  const uint32_t off = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
   if (keep) {
-    const int p = (base + off) & (CAP - 1);
+    const uint32_t p = (base + off) & (CAP - 1);
     st[p] = cs;
     sm[p] = (uint16_t)cm;
   }
   WAVE_SYNC();
-  return base + __popcll(km);
+  return base + (uint32_t)__popcll(km);
 }
 
 __device__ __forceinline__ int wave_max(int v) {
