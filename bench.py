@@ -261,6 +261,8 @@ def main():
                    "lds_stack_capacity": bpida.get_option("lds_stack_capacity"),
                    "nodes_per_round": bpida.get_option("nodes_per_round"),
                    "max_workgroups": bpida.get_option("max_workgroups"),
+                   "donate_every": bpida.get_option("donate_every"),
+                   "donate_min": bpida.get_option("donate_min"),
                    "tuned": bool(tuned) and args.mode == "batched"},
         "instances_per_s": round(n * args.steps / dt, 2),
         "nodes_per_step": nodes_per_step,

@@ -209,6 +209,15 @@ int bpida_server_stop(void);
  *   "max_workgroups"     cap on the persistent search grid (0 = occupancy)
  *   "max_threshold"      stop with BPIDA_ELIMIT before a limit above this
  *                        (-1 = none, default)
+ *   "donate_every"       batched mode: rounds between a workgroup's checks
+ *                        for waiting workgroups to donate to (a power of
+ *                        two in 4..1024, default 128)
+ *   "donate_min"         batched mode: smallest LDS stack (entries) that
+ *                        donates (2..2048; -1 = four rounds' worth of pops,
+ *                        at most half the ring: 256 for 64-node rounds, the
+ *                        default).  Too small a value ships pieces of work
+ *                        that cost more to move than they hold; one the stack
+ *                        seldom reaches stops donation altogether.
  * Returns BPIDA_OK, or BPIDA_EINVAL for an unknown key or a bad value.
  */
 int bpida_set_option(const char *key, int64_t value);

@@ -6,8 +6,11 @@ size class).
     python -m paper_1705_02843_amd.autotune --workload c2_md30_38
 
 Options swept: nodes per round (16: four lanes per node, Alg. 1's map; 64:
-one node per lane), LDS ring capacity, root split depth D, and the size of
-the persistent grid (the occupancy limit or half of it).
+one node per lane), LDS ring capacity, root split depth D, the size of the
+persistent grid (the occupancy limit or half of it), and the donation policy
+(rounds between checks, smallest donating stack).  Large batches sweep a
+smaller set, since one solve takes seconds.  Mixed-width workloads are keyed
+"mixed" instead of by width.
 """
 from __future__ import annotations
 
@@ -20,20 +23,27 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuning", "gfx950.json")
-KEYS = ("nodes_per_round", "lds_stack_capacity", "frontier_depth", "max_workgroups")
+KEYS = ("nodes_per_round", "lds_stack_capacity", "frontier_depth", "max_workgroups",
+        "donate_every", "donate_min")
 
 
 def size_class(n: int) -> str:
     return "small" if n <= 256 else "medium" if n <= 2048 else "large"
 
 
-def candidates(grid_full: int):
+def candidates(grid_full: int, large: bool = False):
     out = []
-    for npl, cap in ((16, 256), (16, 512), (16, 1024), (64, 1024), (64, 2048)):
-        for d in (4, 6, 8, 10):
-            for wg in (0, grid_full // 2):
-                out.append({"nodes_per_round": npl, "lds_stack_capacity": cap,
-                            "frontier_depth": d, "max_workgroups": wg})
+    rings = ((64, 1024), (64, 2048)) if large else ((16, 512), (64, 1024), (64, 2048))
+    depths = (6, 8) if large else (4, 6, 8, 10)
+    grids = (0,) if large else (0, grid_full // 2)
+    for npl, cap in rings:
+        for d in depths:
+            for wg in grids:
+                for de in (64, 128, 256):
+                    for dm in (-1, npl * 2):
+                        out.append({"nodes_per_round": npl, "lds_stack_capacity": cap,
+                                    "frontier_depth": d, "max_workgroups": wg,
+                                    "donate_every": de, "donate_min": dm})
     return out
 
 
@@ -44,21 +54,28 @@ def apply(options: dict) -> None:
             bpida.set_option(k, int(options[k]))
 
 
+def table_key(width: int) -> str:
+    return "mixed" if width == 0 else "w%d" % width
+
+
 def lookup(n: int, width: int = 4, path: str = TABLE):
-    """Tuned options for a batch of n states of this width, or None."""
+    """Tuned options for a batch of n states of this width (0: mixed
+    widths), or None."""
     if not os.path.exists(path):
         return None
     with open(path) as f:
         table = json.load(f)
-    entry = table.get("w%d" % width, {}).get(size_class(n))
+    entry = table.get(table_key(width), {}).get(size_class(n))
     return entry["best"] if entry else None
 
 
-def tune(states: np.ndarray, width: int = 4, reps: int = 2, log=print) -> dict:
+def tune(states: np.ndarray, width: int = 4, reps: int = 2, log=print, widths=None) -> dict:
+    """Sweep the candidates on ``states`` (uint8 [n, w*w], or for a mixed
+    batch the bytes back to back with ``widths`` int32 [n])."""
     import torch
 
     from . import bpida
-    n = states.shape[0]
+    n = states.shape[0] if widths is None else widths.shape[0]
     d_states = torch.from_numpy(np.ascontiguousarray(states)).cuda()
     d_len = torch.empty(n, dtype=torch.int32, device="cuda")
     d_nodes = torch.empty((n, bpida.MAX_THRESHOLDS), dtype=torch.int64, device="cuda")
@@ -67,24 +84,36 @@ def tune(states: np.ndarray, width: int = 4, reps: int = 2, log=print) -> dict:
     ref = None
     results = []
     try:
+        def solve():
+            if widths is not None:
+                return bpida.solve_mixed_device(d_states, widths, d_len, d_nodes)
+            return bpida.solve_device(d_states, d_len, d_nodes, width=width)
+
         bpida.set_option("max_workgroups", 0)
-        rc = bpida.solve_device(d_states, d_len, d_nodes, width=width)
-        if rc != bpida.OK:
-            raise bpida.BpidaError(rc, "autotune reference solve")
-        torch.cuda.synchronize()
+        for _ in range(2):  # the first call sizes the workspace; the second is timed
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc = solve()
+            if rc != bpida.OK:
+                raise bpida.BpidaError(rc, "autotune reference solve")
+            torch.cuda.synchronize()
+            t_ref = time.perf_counter() - t0
+        large = t_ref > 0.5
         grid_full = bpida.last_stats()["grid"]
-        for cfg in candidates(grid_full):
+        for cfg in candidates(grid_full, large):
             apply(cfg)
             best = float("inf")
             for _ in range(reps + 1):  # the first call warms up / sizes the workspace
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                rc = bpida.solve_device(d_states, d_len, d_nodes, width=width)
+                rc = solve()
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t0
                 if rc != bpida.OK:
                     raise bpida.BpidaError(rc, "autotune %r" % cfg)
                 best = min(best, dt)
+                if dt > 4 * t_ref + 0.05:  # far off the default: not worth repeating
+                    break
             out = (d_len.cpu().numpy().copy(), d_nodes.cpu().numpy().copy())
             if ref is None:
                 ref = out
@@ -109,16 +138,26 @@ def main():
     ap.add_argument("--out", default=TABLE)
     args = ap.parse_args()
     from . import instances
-    states = getattr(instances, args.workload)()[0]
-    if args.n:
-        states = states[:args.n]
-    res = tune(states, 4, args.reps)
+    widths = None
+    width = 4
+    if args.workload == "c4_mixed":
+        d = instances.c4_mixed()
+        widths = np.concatenate([np.full(d[w][0].shape[0], w, np.int32) for w in (3, 4, 5)])
+        states = np.concatenate([d[w][0].reshape(-1) for w in (3, 4, 5)])
+        width = 0
+        n = widths.shape[0]
+    else:
+        states = getattr(instances, args.workload)()[0]
+        if args.n:
+            states = states[:args.n]
+        n = states.shape[0]
+    res = tune(states, width, args.reps if n <= 2048 else 0, widths=widths)
     table = {}
     if os.path.exists(args.out):
         with open(args.out) as f:
             table = json.load(f)
     entry = dict(res, workload=args.workload, arch="gfx950")
-    table.setdefault("w4", {})[size_class(states.shape[0])] = entry
+    table.setdefault(table_key(width), {})[size_class(n)] = entry
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1)

@@ -515,6 +515,11 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   // largest growth of one round: a popped node has at most 4 children
   constexpr int kGrow = NPL == 16 ? 32 : 3 * 64;
   const LaneMap M = make_lane_map(lane);
+  // Donating from a shallow stack hands over pieces too small to pay for the
+  // transfer; a threshold the stack seldom reaches stops donation and leaves
+  // subtrees on one workgroup.  Default: four rounds' worth of pops, at most
+  // half the ring.
+  const int dmin = A.donate_min > 0 ? A.donate_min : min(4 * NPL, CAP / 2);
   int smax = INT_MIN;
   uint32_t top = (uint32_t)cnt, bot = 0;  // unsigned: they wrap, top - bot stays small
   while (top != bot) {
@@ -540,7 +545,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
       }
       bot += 64;
       avail -= 64;
-    } else if (avail >= 32 && (tick & 31u) == 0) {
+    } else if (avail >= dmin && (tick & A.donate_mask) == 0) {
       // donation when workgroups wait on tickets no queued chunk covers: the
       // oldest min(128, avail) entries (the shallowest, largest subtrees) are
       // split alternately, so donor and receiver each keep about half

@@ -35,6 +35,8 @@ struct Options {
   int64_t spill_capacity = 16384;
   int64_t max_workgroups = 0;
   int64_t max_threshold = -1;
+  int64_t donate_every = 128;  // batched mode: rounds between donation checks
+  int64_t donate_min = -1;     // batched mode: smallest stack that donates (-1: 4 rounds of pops, <= ring / 2)
 };
 
 std::mutex g_mu;  // serialises solves and option changes
@@ -431,6 +433,8 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
   A.max_limit = (int)(O.max_threshold >= 0 ? std::min<int64_t>(O.max_threshold, kMaxLimit) : kMaxLimit);
   A.idle_ticks = (uint64_t)O.watchdog_ms * (uint64_t)W.wall_khz;
   A.budget_ticks = (uint64_t)O.budget_ms * (uint64_t)W.wall_khz;
+  A.donate_mask = (uint32_t)O.donate_every - 1u;
+  A.donate_min = (int32_t)O.donate_min;
   HIPCHK(launch_batch_setup(A, W.winst.as<InstW>(), W.root_off.as<int64_t>(), W.nroots.as<int32_t>(), st));
   if (timed) HIPCHK(hipEventRecord(W.ev0, st));
   HIPCHK(launch_batch4(cap, npl, (int)grid, A, st));
@@ -735,6 +739,9 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     A.max_limit = (int)(O.max_threshold >= 0 ? std::min<int64_t>(O.max_threshold, kMaxLimit) : kMaxLimit);
     A.idle_ticks = ~0ull;  // waiting for requests is not a stall
     A.budget_ticks = (uint64_t)O.budget_ms * (uint64_t)W.wall_khz;
+    A.donate_mask = (uint32_t)O.donate_every - 1u;
+    A.donate_min = (int32_t)O.donate_min;
+  A.donate_min = (int32_t)O.donate_min;
     A.server = 1;
     A.srv.host = V.host;
     A.srv.req = V.req;
@@ -898,6 +905,12 @@ extern "C" int bpida_set_option(const char* key, int64_t value) {
   } else if (k == "max_threshold") {
     if (value < -1 || value > kMaxLimit) return BPIDA_EINVAL;
     g_opt.max_threshold = value;
+  } else if (k == "donate_every") {
+    if (value < 4 || value > 1024 || (value & (value - 1))) return BPIDA_EINVAL;
+    g_opt.donate_every = value;
+  } else if (k == "donate_min") {
+    if (value != -1 && (value < 2 || value > 2048)) return BPIDA_EINVAL;
+    g_opt.donate_min = value;
   } else {
     return BPIDA_EINVAL;
   }
@@ -918,6 +931,8 @@ extern "C" int64_t bpida_get_option(const char* key) {
   if (k == "spill_capacity") return g_opt.spill_capacity;
   if (k == "max_workgroups") return g_opt.max_workgroups;
   if (k == "max_threshold") return g_opt.max_threshold;
+  if (k == "donate_every") return g_opt.donate_every;
+  if (k == "donate_min") return g_opt.donate_min;
   return INT64_MIN;
 }
 

@@ -73,10 +73,12 @@ def test_options_roundtrip_and_validation(B):
     B.set_option("frontier_depth", old)
     for k, v in (("frontier_depth", 17), ("frontier_depth", -2), ("lds_stack_capacity", 300), ("mode", 2), ("nodes_per_round", 32),
                  ("queue_capacity", -1), ("watchdog_ms", 0),
-                 ("spill_capacity", 65), ("max_threshold", -2), ("no_such_key", 1)):
+                 ("spill_capacity", 65), ("max_threshold", -2), ("donate_every", 48),
+                 ("donate_every", 2), ("donate_min", 0), ("donate_min", 4096), ("no_such_key", 1)):
         with pytest.raises(B.BpidaError):
             B.set_option(k, v)
     assert B.get_option("no_such_key") == -(2 ** 63)
+    assert B.get_option("donate_every") == 128 and B.get_option("donate_min") == -1
 
 
 def test_strerror_covers_codes(B):
