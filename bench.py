@@ -80,7 +80,18 @@ def golden_total(parts):
     return tot
 
 
-def cpu_baseline(parts, budget_nodes, nthreads):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(parts, budget_nodes, nthreads, single_nodes=2.5e8):
     """The oracle, untouched, on a bounded sample: from each part (width) of
     the workload, instances taken in order, skipping any whose stored node
     total alone exceeds a thread's share, until the part's sample holds about
@@ -92,6 +103,20 @@ def cpu_baseline(parts, budget_nodes, nthreads):
             per_part.append([sum(r["nodes"]) for r in json.load(f)["instances"]])
     grand = sum(sum(p) for p in per_part)
     nodes = secs = count = 0
+    # one thread on the smallest instances (the paper's one-core comparison)
+    g0, states0, w0 = max(zip(parts, per_part), key=lambda x: sum(x[1]))[0]
+    per0 = max(per_part, key=sum)
+    order = np.argsort(per0, kind="stable")
+    pick0, tot0 = [], 0
+    for i in order[len(order) // 4:]:
+        pick0.append(int(i))
+        tot0 += per0[i]
+        if tot0 >= single_nodes:
+            break
+    t0 = time.perf_counter()
+    r1 = oracle.solve(states0[sorted(pick0)], w0, nthreads=1)
+    single = r1.total_nodes / (time.perf_counter() - t0)
+    assert r1.rc == 0
     for (g, states, w), per in zip(parts, per_part):
         budget = budget_nodes * sum(per) / grand
         share = max(budget / max(1, nthreads) * 2, min(per))
@@ -112,7 +137,11 @@ def cpu_baseline(parts, budget_nodes, nthreads):
     return {"value": round(nodes / secs, 1), "unit": "nodes/s", "cores": nthreads,
             "kind": "oracle",
             "sample": "%d of the workload's instances (%d nodes, %.1f s wall, %d threads)" % (
-                count, nodes, secs, nthreads)}
+                count, nodes, secs, nthreads),
+            "single_thread_value": round(single, 1),
+            "single_thread_sample": "%d instances from the second quartile up by size (%d nodes)" % (
+                len(pick0), r1.total_nodes),
+            "cpu_model": cpu_model()}
 
 
 def load_traffic(src_hash, mode, workload):
@@ -209,13 +238,17 @@ def main():
             step()
         torch.cuda.synchronize()
         acc = {}
+        per_step = []
         t0 = time.perf_counter()
         for _ in range(steps):
-            step()
+            ts = time.perf_counter()
+            step()  # returns once the results are in device memory
+            per_step.append(time.perf_counter() - ts)
             for k, v in bpida.last_stats().items():
                 acc[k] = acc.get(k, 0) + v
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        acc["median_step_s"] = float(np.median(per_step))
         nodes_step = int(d_nodes.cpu().numpy().view(np.uint64).sum(dtype=np.uint64))
         if expect is not None and nodes_step != expect:
             raise SystemExit("%s: node total %d differs from the stored oracle total %d" % (
@@ -263,8 +296,10 @@ def main():
                    "max_workgroups": bpida.get_option("max_workgroups"),
                    "donate_every": bpida.get_option("donate_every"),
                    "donate_min": bpida.get_option("donate_min"),
+                   "queue_chunk": bpida.get_option("queue_chunk"),
                    "tuned": bool(tuned) and args.mode == "batched"},
         "instances_per_s": round(n * args.steps / dt, 2),
+        "ms_per_step_median": round(acc["median_step_s"] * 1e3, 3),
         "nodes_per_step": nodes_per_step,
         "roofline": {"bound": "alu", "achieved": round(achieved, 1), "peak": round(PEAK_INT_GOPS, 1),
                      "unit": "Gop/s", "frac": round(achieved / PEAK_INT_GOPS, 4),
@@ -298,6 +333,25 @@ def main():
                           "instances_per_s": round(n / odt, 2), "steps": 1, "warmup": 1,
                           "speedup_of_value": round((nodes_per_step / odt) and value / (nodes_per_step / odt), 3)}
         bpida.set_option("mode", MODES[args.mode])
+    if args.mode == "batched":
+        # the host-buffer entry (PCIe copies in and out included), beside `value`
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            if widths is not None:
+                rc, _, hn = bpida.solve_mixed_raw([states[o:o + w * w] for o, w in zip(
+                    np.concatenate([[0], np.cumsum(widths.astype(np.int64) ** 2)[:-1]]), widths)])
+            else:
+                rc, _, hn = bpida.solve_raw(states, width)
+            ts.append(time.perf_counter() - t0)
+            if rc != bpida.OK:
+                raise bpida.BpidaError(rc, "host-buffer solve")
+        if int(hn.sum(dtype=np.uint64)) != nodes_per_step:
+            raise SystemExit("host-buffer solve: node total differs")
+        out["host_buffers"] = {"ms_per_call_median": round(float(np.median(ts[1:])) * 1e3, 3),
+                               "nodes_per_s": round(nodes_per_step / float(np.median(ts[1:])), 1),
+                               "note": "bpida_solve / bpida_solve_mixed on host arrays: "
+                                       "copies in and out included"}
     if not args.no_cpu_baseline:
         nthreads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(parts, args.cpu_budget_nodes, nthreads)

@@ -212,6 +212,10 @@ int bpida_server_stop(void);
  *   "donate_every"       batched mode: rounds between a workgroup's checks
  *                        for waiting workgroups to donate to (a power of
  *                        two in 4..1024, default 128)
+ *   "queue_chunk"        batched mode: entries per donated chunk, 16, 32 or
+ *                        64 (default); a donation splits the oldest
+ *                        2 x queue_chunk entries of the donor's stack
+ *                        alternately.  Overflow spills always move 64.
  *   "donate_min"         batched mode: smallest LDS stack (entries) that
  *                        donates (2..2048; -1 = four rounds' worth of pops,
  *                        at most half the ring: 256 for 64-node rounds, the

@@ -8,7 +8,10 @@ size class).
 Options swept: nodes per round (16: four lanes per node, Alg. 1's map; 64:
 one node per lane), LDS ring capacity, root split depth D, the size of the
 persistent grid (the occupancy limit or half of it), and the donation policy
-(rounds between checks, smallest donating stack).  Large batches sweep a
+(rounds between checks, smallest donating stack, entries per donated chunk).
+The workgroup is always one wave64 (Alg. 1's block = one SIMD unit, so the
+round needs no barrier); the lanes-per-node choice (nodes per round) is the
+workgroup-shape axis.  Large batches sweep a
 smaller set, since one solve takes seconds.  Mixed-width workloads are keyed
 "mixed" instead of by width.
 """
@@ -24,7 +27,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuning", "gfx950.json")
 KEYS = ("nodes_per_round", "lds_stack_capacity", "frontier_depth", "max_workgroups",
-        "donate_every", "donate_min")
+        "donate_every", "donate_min", "queue_chunk")
 
 
 def size_class(n: int) -> str:
@@ -41,9 +44,10 @@ def candidates(grid_full: int, large: bool = False):
             for wg in grids:
                 for de in (64, 128, 256):
                     for dm in (-1, npl * 2):
-                        out.append({"nodes_per_round": npl, "lds_stack_capacity": cap,
-                                    "frontier_depth": d, "max_workgroups": wg,
-                                    "donate_every": de, "donate_min": dm})
+                        for qc in ((64,) if large else (32, 64)):
+                            out.append({"nodes_per_round": npl, "lds_stack_capacity": cap,
+                                        "frontier_depth": d, "max_workgroups": wg,
+                                        "donate_every": de, "donate_min": dm, "queue_chunk": qc})
     return out
 
 

@@ -547,12 +547,12 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
       avail -= 64;
     } else if (avail >= dmin && (tick & A.donate_mask) == 0) {
       // donation when workgroups wait on tickets no queued chunk covers: the
-      // oldest min(128, avail) entries (the shallowest, largest subtrees) are
-      // split alternately, so donor and receiver each keep about half
+      // oldest min(window, avail) entries (the shallowest, largest subtrees)
+      // are split alternately, so donor and receiver each keep about half
       int want = 0;
       if (lane == 0) want = (int64_t)(ld_relaxed(&q->head) - ld_relaxed(&q->tail)) > 0;
       if (wave_bcast(want)) {
-        const int w = min(avail, 128) & ~1;
+        const int w = min(avail, A.donate_window) & ~1;
         const int h = w >> 1;
         const uint32_t pg = (bot + 2u * (uint32_t)lane) & (CAP - 1);
         const uint32_t pk = (bot + 2u * (uint32_t)lane + 1u) & (CAP - 1);

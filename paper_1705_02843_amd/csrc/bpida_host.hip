@@ -37,6 +37,7 @@ struct Options {
   int64_t max_threshold = -1;
   int64_t donate_every = 128;  // batched mode: rounds between donation checks
   int64_t donate_min = -1;     // batched mode: smallest stack that donates (-1: 4 rounds of pops, <= ring / 2)
+  int64_t queue_chunk = 64;    // batched mode: entries per donated chunk (16, 32 or 64)
 };
 
 std::mutex g_mu;  // serialises solves and option changes
@@ -435,6 +436,7 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
   A.budget_ticks = (uint64_t)O.budget_ms * (uint64_t)W.wall_khz;
   A.donate_mask = (uint32_t)O.donate_every - 1u;
   A.donate_min = (int32_t)O.donate_min;
+  A.donate_window = 2 * (int32_t)O.queue_chunk;
   HIPCHK(launch_batch_setup(A, W.winst.as<InstW>(), W.root_off.as<int64_t>(), W.nroots.as<int32_t>(), st));
   if (timed) HIPCHK(hipEventRecord(W.ev0, st));
   HIPCHK(launch_batch4(cap, npl, (int)grid, A, st));
@@ -741,7 +743,10 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     A.budget_ticks = (uint64_t)O.budget_ms * (uint64_t)W.wall_khz;
     A.donate_mask = (uint32_t)O.donate_every - 1u;
     A.donate_min = (int32_t)O.donate_min;
+    A.donate_window = 2 * (int32_t)O.queue_chunk;
+  A.donate_window = 2 * (int32_t)O.queue_chunk;
   A.donate_min = (int32_t)O.donate_min;
+  A.donate_window = 2 * (int32_t)O.queue_chunk;
     A.server = 1;
     A.srv.host = V.host;
     A.srv.req = V.req;
@@ -908,6 +913,9 @@ extern "C" int bpida_set_option(const char* key, int64_t value) {
   } else if (k == "donate_every") {
     if (value < 4 || value > 1024 || (value & (value - 1))) return BPIDA_EINVAL;
     g_opt.donate_every = value;
+  } else if (k == "queue_chunk") {
+    if (value != 16 && value != 32 && value != 64) return BPIDA_EINVAL;
+    g_opt.queue_chunk = value;
   } else if (k == "donate_min") {
     if (value != -1 && (value < 2 || value > 2048)) return BPIDA_EINVAL;
     g_opt.donate_min = value;
@@ -933,6 +941,7 @@ extern "C" int64_t bpida_get_option(const char* key) {
   if (k == "max_threshold") return g_opt.max_threshold;
   if (k == "donate_every") return g_opt.donate_every;
   if (k == "donate_min") return g_opt.donate_min;
+  if (k == "queue_chunk") return g_opt.queue_chunk;
   return INT64_MIN;
 }
 

@@ -220,6 +220,7 @@ struct BatchArgs {
   uint64_t budget_ticks; // every workgroup stops this many ticks after it starts
   uint32_t donate_mask;  // donation checks run when (round & donate_mask) == 0
   int32_t donate_min;    // only stacks of at least this many entries donate (<= 0: 4 rounds of pops, <= ring / 2)
+  int32_t donate_window; // a donation splits the oldest min(window, stack) entries (2 x chunk)
   int32_t server;        // nonzero: continuous-batching server (srv below)
   ServerArgs srv;
 };
