@@ -144,6 +144,61 @@ def cpu_baseline(parts, budget_nodes, nthreads, single_nodes=2.5e8):
             "cpu_model": cpu_model()}
 
 
+def first_solution_leg(bpida, part, states, width, d_states, d_len, d_nodes, stream, with_cpu,
+                       sample_nodes=6e8):
+    """The final limit stopping at its first goal (Alg. 1 as printed; the
+    semantics of the paper's single-core comparison): the GPU on the whole
+    batch, and the GPU and the oracle on one host thread on the same bounded
+    sample.  Context, not the metric."""
+    import torch
+    bpida.set_option("first_solution", 1)
+    try:
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            rc = bpida.solve_device(d_states, d_len, d_nodes, width=width, stream=stream)
+            ts.append(time.perf_counter() - t0)
+            if rc != bpida.OK:
+                raise bpida.BpidaError(rc, "first-solution solve")
+        torch.cuda.synchronize()
+        n = states.shape[0]
+        res = {"gpu_ms_per_step": round(float(np.median(ts)) * 1e3, 3),
+               "gpu_instances_per_s": round(n / float(np.median(ts)), 2),
+               "nodes_per_step": int(d_nodes.cpu().numpy().view(np.uint64).sum(dtype=np.uint64))}
+        if not with_cpu:
+            return res
+        with open(os.path.join(ROOT, "tests", "golden", part[0] + ".json")) as f:
+            per = [sum(r["nodes"]) for r in json.load(f)["instances"]]
+        pick, tot = [], 0
+        for i, c in enumerate(per):
+            if c > sample_nodes / 4:
+                continue
+            pick.append(i)
+            tot += c
+            if tot >= sample_nodes:
+                break
+        sub = np.ascontiguousarray(states[pick])
+        gs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            rc, _, _ = bpida.solve_raw(sub, width)
+            gs.append(time.perf_counter() - t0)
+            if rc != bpida.OK:
+                raise bpida.BpidaError(rc, "first-solution sample")
+    finally:
+        bpida.set_option("first_solution", 0)
+    from oracle import oracle
+    t0 = time.perf_counter()
+    r = oracle.solve(sub, width, nthreads=1, first_solution=True)
+    cpu = time.perf_counter() - t0
+    assert r.rc == 0
+    res.update({"sample": "%d instances (oracle: %d nodes)" % (len(pick), r.total_nodes),
+                "sample_gpu_ms": round(float(np.median(gs)) * 1e3, 3),
+                "sample_oracle_one_thread_ms": round(cpu * 1e3, 1),
+                "speedup_vs_one_core": round(cpu / float(np.median(gs)), 1)})
+    return res
+
+
 def load_traffic(src_hash, mode, workload):
     """Per-launch HBM bytes of the timed search kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
@@ -174,6 +229,8 @@ def main():
     ap.add_argument("--untuned", action="store_true",
                     help="ignore the autotuner's table (paper_1705_02843_amd/tuning/) and use the "
                          "library defaults")
+    ap.add_argument("--no-first-solution", action="store_true",
+                    help="skip the first-solution leg (final limit stops at its first goal)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -352,6 +409,9 @@ def main():
                                "nodes_per_s": round(nodes_per_step / float(np.median(ts[1:])), 1),
                                "note": "bpida_solve / bpida_solve_mixed on host arrays: "
                                        "copies in and out included"}
+    if args.mode == "batched" and widths is None and not args.no_first_solution:
+        out["first_solution"] = first_solution_leg(bpida, parts[0], states, width, d_states, d_len,
+                                                   d_nodes, stream, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         nthreads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(parts, args.cpu_budget_nodes, nthreads)

@@ -212,6 +212,14 @@ int bpida_server_stop(void);
  *   "donate_every"       batched mode: rounds between a workgroup's checks
  *                        for waiting workgroups to donate to (a power of
  *                        two in 4..1024, default 128)
+ *   "first_solution"     0 (default): the final limit runs to completion (all
+ *                        optimal solutions, Sec. 6.1), so every count is
+ *                        unique.  1: the final limit stops at its first goal
+ *                        (Alg. 1 as printed): out_len and the counts of the
+ *                        earlier limits are unchanged; the final column
+ *                        holds the nodes expanded before the search stopped
+ *                        (at most the all-solutions count, and it varies
+ *                        from run to run).
  *   "queue_chunk"        batched mode: entries per donated chunk, 16, 32 or
  *                        64 (default); a donation splits the oldest
  *                        2 x queue_chunk entries of the donor's stack

@@ -23,7 +23,9 @@
  *   - the first limit is h(start) (DecideFirstLimit);
  *   - goal test on expansion (Alg. 1 and Alg. 2 test the popped node);
  *   - the final iteration runs to completion (Sec. 6.1, all optimal
- *     solutions), so its count is unique;
+ *     solutions), so its count is unique; a first-solution mode instead
+ *     returns at the first goal expanded, as Alg. 1 is printed (the count of
+ *     the final iteration is then that of this sequential U, L, R, D order);
  *   - "expanded" = every node the DFS visits, start and goal nodes included.
  *
  * Output per instance: the optimal length, the sequence of f-limits used and
@@ -79,6 +81,7 @@ typedef struct {
   int found;        /* a goal was expanded in this iteration               */
   int fmin;         /* smallest f of a pruned child (next f-limit)         */
   int check;        /* recompute h from scratch at every node              */
+  int first;        /* first-solution mode: stop at the first goal         */
   int hbad;         /* check mode found a mismatch                         */
   uint8_t s[ORACLE_MAX_CELLS];
 } search_t;
@@ -89,9 +92,13 @@ static void dfs(search_t *S, int blank, int g, int h, int last) {
   const int w = S->w;
   S->count++;
   if (S->check && md_full(w, S->s) != h) S->hbad = 1;
-  if (h == 0 && is_goal(w, S->s)) S->found = 1; /* all solutions: continue */
+  if (h == 0 && is_goal(w, S->s)) {
+    S->found = 1;
+    if (S->first) return; /* first solution: the search ends here */
+  }                       /* all solutions: continue */
   const int r = blank / w, c = blank % w;
   for (int a = 0; a < 4; ++a) {
+    if (S->first && S->found) return;
     if (last >= 0 && a == 3 - last) continue; /* undoes the parent move */
     int n;
     if (a == 0) { if (r == 0) continue; n = blank - w; }
@@ -146,8 +153,8 @@ int oracle_check_state(const uint8_t *s, int32_t w) {
 int32_t oracle_manhattan(const uint8_t *s, int32_t w) { return md_full(w, s); }
 
 /* Solve one instance.  limits[j], nodes[j] for j < *niter. */
-static int solve_one(const uint8_t *start, int w, int check, int max_limit, int32_t *len,
-                     int32_t *limits, uint64_t *nodes, int32_t *niter) {
+static int solve_one(const uint8_t *start, int w, int check, int first, int max_limit,
+                     int32_t *len, int32_t *limits, uint64_t *nodes, int32_t *niter) {
   *len = -1;
   *niter = 0;
   for (int j = 0; j < ORACLE_MAX_ITERS; ++j) { limits[j] = 0; nodes[j] = 0; }
@@ -157,6 +164,7 @@ static int solve_one(const uint8_t *start, int w, int check, int max_limit, int3
   memset(&S, 0, sizeof S);
   S.w = w;
   S.check = check;
+  S.first = first;
   memcpy(S.s, start, (size_t)(w * w));
   int blank = 0;
   while (start[blank] != 0) ++blank;
@@ -183,7 +191,7 @@ static int solve_one(const uint8_t *start, int w, int check, int max_limit, int3
 
 typedef struct {
   const uint8_t *states;
-  int n, w, check, max_limit;
+  int n, w, check, first, max_limit;
   int32_t *len, *limits, *niter, *status;
   uint64_t *nodes;
   int next; /* shared cursor, taken under the lock */
@@ -198,7 +206,8 @@ static void *worker(void *arg) {
     pthread_mutex_unlock(&B->mu);
     if (i >= B->n) break;
     const int nn = B->w * B->w;
-    B->status[i] = solve_one(B->states + (size_t)i * nn, B->w, B->check, B->max_limit, &B->len[i],
+    B->status[i] = solve_one(B->states + (size_t)i * nn, B->w, B->check, B->first, B->max_limit,
+                             &B->len[i],
                              B->limits + (size_t)i * ORACLE_MAX_ITERS,
                              B->nodes + (size_t)i * ORACLE_MAX_ITERS, &B->niter[i]);
   }
@@ -215,16 +224,19 @@ static void *worker(void *arg) {
  * nthreads   worker threads (<= 0: one)
  * check      nonzero: recompute h from scratch at every node
  * max_limit  stop with ORACLE_ELIMIT before an f-limit above this (< 0: none)
+ * first      nonzero: the final iteration returns at its first goal
  * Returns ORACLE_OK if every instance solved, else the first failing code.
  */
 int oracle_solve(const uint8_t *states, int32_t n, int32_t width, int32_t *out_len,
                  int32_t *out_limits, uint64_t *out_nodes, int32_t *out_niter,
-                 int32_t *out_status, int32_t nthreads, int32_t check, int32_t max_limit) {
+                 int32_t *out_status, int32_t nthreads, int32_t check, int32_t max_limit,
+                 int32_t first) {
   if (!states || !out_len || !out_limits || !out_nodes || !out_niter || !out_status || n < 0 ||
       width < 2 || width > ORACLE_MAX_WIDTH)
     return ORACLE_EINVAL;
   batch_t B;
-  B.states = states; B.n = n; B.w = width; B.check = check; B.max_limit = max_limit;
+  B.states = states; B.n = n; B.w = width; B.check = check; B.first = first;
+  B.max_limit = max_limit;
   B.len = out_len; B.limits = out_limits; B.nodes = out_nodes; B.niter = out_niter;
   B.status = out_status; B.next = 0;
   pthread_mutex_init(&B.mu, NULL);

@@ -48,7 +48,7 @@ def _load():
         lib.oracle_solve.argtypes = [p(ctypes.c_uint8), ctypes.c_int32, ctypes.c_int32,
                                      p(ctypes.c_int32), p(ctypes.c_int32), p(ctypes.c_uint64),
                                      p(ctypes.c_int32), p(ctypes.c_int32), ctypes.c_int32,
-                                     ctypes.c_int32, ctypes.c_int32]
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         lib.oracle_solve.restype = ctypes.c_int32
         lib.oracle_check_state.argtypes = [p(ctypes.c_uint8), ctypes.c_int32]
         lib.oracle_check_state.restype = ctypes.c_int32
@@ -77,7 +77,9 @@ class OracleResult:
 
 
 def solve(states, width: int, nthreads: int = 1, check: bool = False,
-          max_limit: int = -1) -> OracleResult:
+          max_limit: int = -1, first_solution: bool = False) -> OracleResult:
+    """IDA* per instance (all optimal solutions in the final iteration, or
+    with ``first_solution`` stopping at its first goal, as Alg. 1 returns)."""
     lib = _load()
     st = np.ascontiguousarray(np.asarray(states, dtype=np.uint8).reshape(-1, width * width))
     n = st.shape[0]
@@ -91,7 +93,8 @@ def solve(states, width: int, nthreads: int = 1, check: bool = False,
     rc = lib.oracle_solve(_ptr(st, ctypes.c_uint8), n, width, _ptr(length, ctypes.c_int32),
                           _ptr(limits, ctypes.c_int32), _ptr(nodes, ctypes.c_uint64),
                           _ptr(niter, ctypes.c_int32), _ptr(status, ctypes.c_int32),
-                          int(nthreads), int(bool(check)), int(max_limit))
+                          int(nthreads), int(bool(check)), int(max_limit),
+                          int(bool(first_solution)))
     return OracleResult(int(rc), length, limits, nodes, niter, status)
 
 

@@ -140,7 +140,9 @@ __device__ bool seed_limit(const BatchArgs& A, int i, uint64_t* stage, uint16_t*
   const bool wide = S->width == 5;
   if (lane == 0) __hip_atomic_store(&S->outstanding, 1, __ATOMIC_RELAXED, AGENT);
   const NodeW* roots = A.tree + S->root_off;
-  const int nroots = S->nroots;
+  // first-solution mode: a goal inside the split tree ends the search at
+  // this limit without searching any subtree
+  const int nroots = (A.first_solution && A.goal_g[i] <= L) ? 0 : S->nroots;
   int fm = INT_MAX;
   bool full = false;
   for (int base = 0; base < nroots && !full; base += 64) {
@@ -450,6 +452,7 @@ __device__ void admitter_loop(const BatchArgs& A, uint64_t* st, uint16_t* sm, ui
     S.nodes = 0;
     S.fmin = INT_MAX;
     S.goals = 0;
+    S.stop = 0;
     S.root_off = (int64_t)slot * V.stride;
     S.nroots = 0;
     S.width = 4;
@@ -522,6 +525,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   const int dmin = A.donate_min > 0 ? A.donate_min : min(4 * NPL, CAP / 2);
   int smax = INT_MIN;
   uint32_t top = (uint32_t)cnt, bot = 0;  // unsigned: they wrap, top - bot stays small
+  if (A.first_solution && wave_bcast(lane == 0 ? ld_relaxed(&A.is[inst].stop) : 0)) top = bot;
   while (top != bot) {
     int avail = (int)(top - bot);
     ++tick;
@@ -585,6 +589,16 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
     }
     expanded += (uint64_t)kp;
     wc.rounds += 1;
+    if (A.first_solution) {
+      // first-solution mode (Alg. 1 returns at its first goal): the unit that
+      // expands a goal stops its instance; the others see the flag within 64
+      // rounds and drop their stacks
+      if (goals > 0) {
+        if (lane == 0) __hip_atomic_store(&A.is[inst].stop, 1, __ATOMIC_RELAXED, AGENT);
+        break;
+      }
+      if ((tick & 63u) == 0 && wave_bcast(lane == 0 ? ld_relaxed(&A.is[inst].stop) : 0)) break;
+    }
   }
   if (NPL == 64) {
     const int sm_w = wave_max(smax);
@@ -752,6 +766,7 @@ __global__ void batch_setup_kernel(BatchArgs A, const InstW* __restrict__ inst,
     S.nodes = 0;
     S.fmin = INT_MAX;
     S.goals = 0;
+    S.stop = 0;
     S.root_off = root_off[k];
     S.nroots = nroots[k];
     S.width = inst[k].width;

@@ -38,6 +38,7 @@ struct Options {
   int64_t donate_every = 128;  // batched mode: rounds between donation checks
   int64_t donate_min = -1;     // batched mode: smallest stack that donates (-1: 4 rounds of pops, <= ring / 2)
   int64_t queue_chunk = 64;    // batched mode: entries per donated chunk (16, 32 or 64)
+  int64_t first_solution = 0;  // 1: the final limit stops at its first goal (Alg. 1 as printed)
 };
 
 std::mutex g_mu;  // serialises solves and option changes
@@ -82,7 +83,7 @@ struct Workspace {
   int wall_khz = 100000;
   bool arch_ok = false;
   uint64_t qcap = 0;  // queue slots of the last batched launch
-  DevBuf inst, tree, tree_off, hist, goal_g, err, cursor, part, spill_t, spill_m, res;
+  DevBuf inst, tree, tree_off, hist, goal_g, err, cursor, part, spill_t, spill_m, res, stop;
   DevBuf qctl, qseq, qslots, istate, root_off, nroots, status, walks;
   // non-backtracking walk counts per width (3, 4, 5), start cell and length
   int32_t h_walks[3][kWalkCells][kMaxDepth + 1];
@@ -246,6 +247,7 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
   HIPCHK(W.spill_t.ensure(sizeof(uint64_t) * (size_t)max_grid * spill_cap));
   HIPCHK(W.spill_m.ensure(sizeof(uint16_t) * (size_t)max_grid * spill_cap));
   HIPCHK(W.cursor.ensure(sizeof(int32_t)));
+  HIPCHK(W.stop.ensure(sizeof(int32_t)));
   HIPCHK(W.res.ensure(sizeof(LimitResult)));
   HIPCHK(launch_zero_i32(W.cursor.as<int32_t>(), 1, st));
 
@@ -260,10 +262,15 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
       code = BPIDA_ELIMIT;
       for (int j = 0; j < BPIDA_MAX_THRESHOLDS; ++j) {
         if (L > kMaxLimit || (O.max_threshold >= 0 && L > O.max_threshold)) break;
+        int32_t* stop = nullptr;
+        if (O.first_solution) {
+          stop = W.stop.as<int32_t>();
+          HIPCHK(launch_zero_i32(stop, 1, st));
+        }
         HIPCHK(hipEventRecord(W.ev0, st));
         HIPCHK(launch_search4(cap, grid, roots, nroots, L, W.cursor.as<int32_t>(),
                               W.spill_t.as<uint64_t>(), W.spill_m.as<uint16_t>(), spill_cap,
-                              W.part.as<Partial>(), st));
+                              W.part.as<Partial>(), stop, st));
         HIPCHK(hipEventRecord(W.ev1, st));
         HIPCHK(launch_reduce(W.part.as<Partial>(), grid, W.hist.as<uint32_t>() + (size_t)i * kHistBins,
                              W.goal_g.as<int32_t>() + i, L, j, d_nodes + (size_t)i * BPIDA_MAX_THRESHOLDS,
@@ -437,6 +444,7 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
   A.donate_mask = (uint32_t)O.donate_every - 1u;
   A.donate_min = (int32_t)O.donate_min;
   A.donate_window = 2 * (int32_t)O.queue_chunk;
+  A.first_solution = (int32_t)O.first_solution;
   HIPCHK(launch_batch_setup(A, W.winst.as<InstW>(), W.root_off.as<int64_t>(), W.nroots.as<int32_t>(), st));
   if (timed) HIPCHK(hipEventRecord(W.ev0, st));
   HIPCHK(launch_batch4(cap, npl, (int)grid, A, st));
@@ -744,9 +752,7 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     A.donate_mask = (uint32_t)O.donate_every - 1u;
     A.donate_min = (int32_t)O.donate_min;
     A.donate_window = 2 * (int32_t)O.queue_chunk;
-  A.donate_window = 2 * (int32_t)O.queue_chunk;
-  A.donate_min = (int32_t)O.donate_min;
-  A.donate_window = 2 * (int32_t)O.queue_chunk;
+    A.first_solution = (int32_t)O.first_solution;
     A.server = 1;
     A.srv.host = V.host;
     A.srv.req = V.req;
@@ -913,6 +919,9 @@ extern "C" int bpida_set_option(const char* key, int64_t value) {
   } else if (k == "donate_every") {
     if (value < 4 || value > 1024 || (value & (value - 1))) return BPIDA_EINVAL;
     g_opt.donate_every = value;
+  } else if (k == "first_solution") {
+    if (value != 0 && value != 1) return BPIDA_EINVAL;
+    g_opt.first_solution = value;
   } else if (k == "queue_chunk") {
     if (value != 16 && value != 32 && value != 64) return BPIDA_EINVAL;
     g_opt.queue_chunk = value;
@@ -942,6 +951,7 @@ extern "C" int64_t bpida_get_option(const char* key) {
   if (k == "donate_every") return g_opt.donate_every;
   if (k == "donate_min") return g_opt.donate_min;
   if (k == "queue_chunk") return g_opt.queue_chunk;
+  if (k == "first_solution") return g_opt.first_solution;
   return INT64_MIN;
 }
 

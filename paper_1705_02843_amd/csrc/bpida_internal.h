@@ -147,6 +147,7 @@ struct InstState {
   int64_t root_off;     // first root of this instance in the split tree buffer
   int32_t nroots;
   int32_t width;        // board width 3, 4 or 5
+  int32_t stop;         // first-solution mode: a goal was expanded, drop the rest
 };
 
 // Queue control block and run counters.  The fields that many workgroups
@@ -221,6 +222,7 @@ struct BatchArgs {
   uint32_t donate_mask;  // donation checks run when (round & donate_mask) == 0
   int32_t donate_min;    // only stacks of at least this many entries donate (<= 0: 4 rounds of pops, <= ring / 2)
   int32_t donate_window; // a donation splits the oldest min(window, stack) entries (2 x chunk)
+  int32_t first_solution; // nonzero: the final limit stops at its first goal
   int32_t server;        // nonzero: continuous-batching server (srv below)
   ServerArgs srv;
 };
@@ -248,7 +250,7 @@ hipError_t launch_split4(const Inst* d_inst, int n, int depth, const int64_t* d_
                          hipStream_t s);
 hipError_t launch_search4(int lds_cap, int grid, const Node* d_roots, int nroots, int limit,
                           int32_t* d_cursor, uint64_t* d_spill_tiles, uint16_t* d_spill_meta,
-                          int spill_cap, Partial* d_part, hipStream_t s);
+                          int spill_cap, Partial* d_part, int32_t* d_stop, hipStream_t s);
 hipError_t launch_reduce(const Partial* d_part, int nwg, const uint32_t* d_hist_i,
                          const int32_t* d_goal_g_i, int limit, int col, uint64_t* d_nodes_row,
                          int32_t* d_cursor, LimitResult* d_res, hipStream_t s);

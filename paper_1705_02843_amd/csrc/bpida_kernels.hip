@@ -182,7 +182,7 @@ hipError_t launch_split4(const Inst* d_inst, int n, int depth, const int64_t* d_
 // roots through an atomic cursor and searches each to completion.
 //
 // LDS stack: a ring of CAP entries, SoA (u64 tiles, u16 meta), positions
-// [bot, top) used.  Stack meta: bits 0..3 blank, 4..6 forbidden move
+// [bot, top) used.  Stack meta: bits 0..4 blank, 5..7 forbidden move
 // (4 = none), 8..15 slack = limit - g - h (>= 0; a child has slack - 1 - dh).
 // When a round could overflow the ring, the 64 oldest entries move to this
 // workgroup's HBM spill stack; when fewer than 16 entries remain and the
@@ -198,7 +198,10 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
                                                      int limit, int32_t* __restrict__ cursor,
                                                      uint64_t* __restrict__ spill_tiles,
                                                      uint16_t* __restrict__ spill_meta,
-                                                     int spill_cap, Partial* __restrict__ part) {
+                                                     int spill_cap, Partial* __restrict__ part,
+                                                     int32_t* __restrict__ stop) {
+  // stop: null, or (first-solution mode) a flag the workgroup that expands a
+  // goal sets; the others see it within 64 rounds and drop their work
   static_assert((CAP & (CAP - 1)) == 0 && CAP >= 128, "ring size");
   __shared__ uint64_t st[CAP];
   __shared__ uint16_t sm[CAP];
@@ -215,7 +218,10 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
   int err = 0;
   int spill_hw = 0;
 
+  bool stopped = false;
   for (;;) {
+    if (stop && wave_bcast(lane == 0 ? __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0))
+      break;
     int r = 0;
     if (lane == 0) r = atomicAdd(cursor, 1);
     r = __builtin_amdgcn_readfirstlane(__shfl(r, 0, 64));
@@ -264,7 +270,20 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
       top = bp_round<CAP>(st, sm, top, kp, limit, M, goals, fmin);
       expanded += (uint64_t)kp;
       rounds += 1;
+      if (stop) {
+        if (goals > 0) {
+          if (lane == 0) __hip_atomic_store(stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          stopped = true;
+          break;
+        }
+        if ((rounds & 63u) == 0 &&
+            wave_bcast(lane == 0 ? __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0)) {
+          stopped = true;
+          break;
+        }
+      }
     }
+    if (stopped) break;
   }
   fmin = wave_min(fmin);
   if (lane == 0) {
@@ -283,32 +302,23 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
 template <int CAP>
 static hipError_t launch_search4_t(int grid, const Node* d_roots, int nroots, int limit,
                                    int32_t* d_cursor, uint64_t* d_st, uint16_t* d_sm, int spill_cap,
-                                   Partial* d_part, hipStream_t s) {
+                                   Partial* d_part, int32_t* d_stop, hipStream_t s) {
   hipLaunchKernelGGL(search4_kernel<CAP>, dim3(grid), dim3(64), 0, s, d_roots, nroots, limit,
-                     d_cursor, d_st, d_sm, spill_cap, d_part);
+                     d_cursor, d_st, d_sm, spill_cap, d_part, d_stop);
   return hipGetLastError();
 }
 
 hipError_t launch_search4(int lds_cap, int grid, const Node* d_roots, int nroots, int limit,
                           int32_t* d_cursor, uint64_t* d_spill_tiles, uint16_t* d_spill_meta,
-                          int spill_cap, Partial* d_part, hipStream_t s) {
+                          int spill_cap, Partial* d_part, int32_t* d_stop, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   switch (lds_cap) {
-    case 128:
-      return launch_search4_t<128>(grid, d_roots, nroots, limit, d_cursor, d_spill_tiles,
-                                   d_spill_meta, spill_cap, d_part, s);
-    case 256:
-      return launch_search4_t<256>(grid, d_roots, nroots, limit, d_cursor, d_spill_tiles,
-                                   d_spill_meta, spill_cap, d_part, s);
-    case 512:
-      return launch_search4_t<512>(grid, d_roots, nroots, limit, d_cursor, d_spill_tiles,
-                                   d_spill_meta, spill_cap, d_part, s);
-    case 1024:
-      return launch_search4_t<1024>(grid, d_roots, nroots, limit, d_cursor, d_spill_tiles,
-                                    d_spill_meta, spill_cap, d_part, s);
-    case 2048:
-      return launch_search4_t<2048>(grid, d_roots, nroots, limit, d_cursor, d_spill_tiles,
-                                    d_spill_meta, spill_cap, d_part, s);
+#define CASE(C)                                                                                 \
+  case C:                                                                                       \
+    return launch_search4_t<C>(grid, d_roots, nroots, limit, d_cursor, d_spill_tiles,           \
+                               d_spill_meta, spill_cap, d_part, d_stop, s);
+    CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048)
+#undef CASE
     default:
       return hipErrorInvalidValue;
   }

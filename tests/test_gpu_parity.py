@@ -32,7 +32,7 @@ def B():
 
 OPTION_KEYS = ("mode", "frontier_depth", "lds_stack_capacity", "spill_capacity",
                "max_workgroups", "max_threshold", "queue_capacity", "watchdog_ms",
-               "nodes_per_round", "budget_ms")
+               "nodes_per_round", "budget_ms", "first_solution")
 # plain: one launch per instance and limit, 16-node rounds (Alg. 1's map);
 # batched: persistent launch, 64-node rounds; batched16: persistent, 16-node
 MODES = {"plain": {"mode": 0}, "batched": {"mode": 1, "nodes_per_round": 64},

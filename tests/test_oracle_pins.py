@@ -84,6 +84,27 @@ def test_3x3_lengths_equal_bfs_for_every_state(bfs3):
     np.testing.assert_array_equal(r.length, want)
 
 
+def test_3x3_first_solution_mode(bfs3):
+    """First-solution mode (Alg. 1 returns at its first goal) on every 3x3
+    state: the length is the BFS distance, every earlier iteration is the
+    all-solutions count, and the final count lies between the L + 1 nodes of
+    the path to the goal found and the all-solutions count."""
+    states = list(bfs3.keys())
+    a = _solve(states, 3)
+    b = _solve(states, 3, first_solution=True)
+    assert a.rc == 0 and b.rc == 0
+    want = np.array([bfs3[s] for s in states], np.int32)
+    np.testing.assert_array_equal(b.length, want)
+    np.testing.assert_array_equal(b.niter, a.niter)
+    k = a.niter - 1
+    rows = np.arange(len(states))
+    mask = np.arange(a.nodes.shape[1])[None, :] < k[:, None]
+    np.testing.assert_array_equal(np.where(mask, b.nodes, 0), np.where(mask, a.nodes, 0))
+    fin_b, fin_a = b.nodes[rows, k], a.nodes[rows, k]
+    assert (fin_b >= want.astype(np.uint64) + 1).all() and (fin_b <= fin_a).all()
+    assert (fin_b < fin_a).any()  # it does stop early somewhere
+
+
 def test_3x3_manhattan_admissible_parity_consistent(bfs3):
     for s, d in bfs3.items():
         h = oracle.manhattan(np.array(s, np.uint8), 3)
