@@ -212,6 +212,13 @@ int bpida_server_stop(void);
  *   "donate_every"       batched mode: rounds between a workgroup's checks
  *                        for waiting workgroups to donate to (a power of
  *                        two in 4..1024, default 128)
+ *   "static_lb"          plain mode: 1 (default) re-splits, between limits, every
+ *                        root whose repetition count exceeded the average of
+ *                        the searched roots (Sec. 5, BPIDA*'s static load
+ *                        balancing): it is replaced by the nodes of its
+ *                        subtree at the first depth holding at least
+ *                        load / average of them (at most 64); 0 keeps the
+ *                        root set of the split.  Counts are exact either way.
  *   "first_solution"     0 (default): the final limit runs to completion (all
  *                        optimal solutions, Sec. 6.1), so every count is
  *                        unique.  1: the final limit stops at its first goal
@@ -258,6 +265,7 @@ int64_t bpida_get_option(const char *key);
  *          dropped, 4 idle watchdog, 8 deadline, 16 queue ring full,
  *          256 split check)
  *   out[14] batched mode: work-queue slots (chunks of 64 entries)
+ *   out[15] plain mode: roots added by the static load balancing
  * n = number of slots to fill (<= 16).  Returns BPIDA_OK or BPIDA_EINVAL.
  */
 int bpida_last_stats(uint64_t *out, int32_t n);

@@ -95,7 +95,7 @@ def last_stats() -> dict:
         raise BpidaError(rc, "last_stats")
     keys = ("rounds", "search_nodes", "spilled", "launches", "search_us", "spill_high_water",
             "chunks_pushed", "chunks_popped", "wg_us_search", "wg_us_queue", "wg_us_idle",
-            "donations_voluntary", "grid", "error_bits", "queue_slots")
+            "donations_voluntary", "grid", "error_bits", "queue_slots", "lb_roots_added")
     return {k: int(out[i]) for i, k in enumerate(keys)}
 
 

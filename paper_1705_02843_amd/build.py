@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbpida.so")
-SOURCES = ["bpida_kernels.hip", "bpida_batch.hip", "bpida_host.hip"]
+SOURCES = ["bpida_kernels.hip", "bpida_batch.hip", "bpida_lb.hip", "bpida_host.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

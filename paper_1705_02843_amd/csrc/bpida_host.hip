@@ -39,6 +39,7 @@ struct Options {
   int64_t donate_min = -1;     // batched mode: smallest stack that donates (-1: 4 rounds of pops, <= ring / 2)
   int64_t queue_chunk = 64;    // batched mode: entries per donated chunk (16, 32 or 64)
   int64_t first_solution = 0;  // 1: the final limit stops at its first goal (Alg. 1 as printed)
+  int64_t static_lb = 1;       // plain mode: re-split heavy roots between limits (Sec. 5)
 };
 
 std::mutex g_mu;  // serialises solves and option changes
@@ -89,6 +90,7 @@ struct Workspace {
   int32_t h_walks[3][kWalkCells][kMaxDepth + 1];
   DevBuf treew, winst, tree_offw, widths, byte_off;
   DevBuf h2d_states, out_len, out_nodes;
+  DevBuf lb_load, lb_roots[2], lb_level, lb_count, lb_off, lb_avg, lb_total;
   LimitResult* h_res = nullptr;  // pinned
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
@@ -248,6 +250,20 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
   HIPCHK(W.spill_m.ensure(sizeof(uint16_t) * (size_t)max_grid * spill_cap));
   HIPCHK(W.cursor.ensure(sizeof(int32_t)));
   HIPCHK(W.stop.ensure(sizeof(int32_t)));
+  // static load balancing: a root list grows to at most lb_cap entries
+  int64_t max_roots = 0;
+  for (int i = 0; i < n; ++i) max_roots = std::max<int64_t>(max_roots, lc[(size_t)i * L1 + D]);
+  const int64_t lb_cap = O.static_lb ? max_roots * 32 + 4096 : 0;
+  if (O.static_lb) {
+    HIPCHK(W.lb_load.ensure(sizeof(uint32_t) * (size_t)lb_cap));
+    HIPCHK(W.lb_roots[0].ensure(sizeof(Node) * (size_t)lb_cap));
+    HIPCHK(W.lb_roots[1].ensure(sizeof(Node) * (size_t)lb_cap));
+    HIPCHK(W.lb_level.ensure(sizeof(int32_t) * (size_t)lb_cap));
+    HIPCHK(W.lb_count.ensure(sizeof(int32_t) * (size_t)lb_cap));
+    HIPCHK(W.lb_off.ensure(sizeof(int64_t) * (size_t)lb_cap));
+    HIPCHK(W.lb_avg.ensure(2 * sizeof(uint64_t)));
+    HIPCHK(W.lb_total.ensure(sizeof(int64_t)));
+  }
   HIPCHK(W.res.ensure(sizeof(LimitResult)));
   HIPCHK(launch_zero_i32(W.cursor.as<int32_t>(), 1, st));
 
@@ -255,13 +271,19 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
   for (int i = 0; i < n; ++i) {
     int code = inst[i].status;
     if (code == BPIDA_OK) {
-      const int nroots = lc[(size_t)i * L1 + D];
+      int nroots = lc[(size_t)i * L1 + D];
       const Node* roots = W.tree.as<Node>() + root_off[i];
-      const int grid = (int)std::min<int64_t>(nroots, max_grid);
+      int pong = 0;
       int L = inst[i].h0;
       code = BPIDA_ELIMIT;
       for (int j = 0; j < BPIDA_MAX_THRESHOLDS; ++j) {
         if (L > kMaxLimit || (O.max_threshold >= 0 && L > O.max_threshold)) break;
+        const int grid = (int)std::min<int64_t>(nroots, max_grid);
+        uint32_t* load = nullptr;
+        if (O.static_lb) {
+          load = W.lb_load.as<uint32_t>();
+          HIPCHK(launch_zero_i32((int32_t*)load, nroots, st));
+        }
         int32_t* stop = nullptr;
         if (O.first_solution) {
           stop = W.stop.as<int32_t>();
@@ -270,7 +292,7 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
         HIPCHK(hipEventRecord(W.ev0, st));
         HIPCHK(launch_search4(cap, grid, roots, nroots, L, W.cursor.as<int32_t>(),
                               W.spill_t.as<uint64_t>(), W.spill_m.as<uint16_t>(), spill_cap,
-                              W.part.as<Partial>(), stop, st));
+                              W.part.as<Partial>(), stop, load, st));
         HIPCHK(hipEventRecord(W.ev1, st));
         HIPCHK(launch_reduce(W.part.as<Partial>(), grid, W.hist.as<uint32_t>() + (size_t)i * kHistBins,
                              W.goal_g.as<int32_t>() + i, L, j, d_nodes + (size_t)i * BPIDA_MAX_THRESHOLDS,
@@ -298,6 +320,35 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
         if (R.fnext != L + 2) {
           code = BPIDA_EINTERNAL;
           break;
+        }
+        if (O.static_lb && nroots > 0) {
+          // Sec. 5: re-split the roots whose repetition count exceeded the
+          // average, for the next iteration
+          HIPCHK(launch_lb_plan(roots, load, nroots, L, W.lb_avg.as<uint64_t>(),
+                                W.lb_level.as<int32_t>(), W.lb_count.as<int32_t>(),
+                                W.lb_off.as<int64_t>(), W.lb_total.as<int64_t>(), st));
+          int64_t total = 0;
+          HIPCHK(hipMemcpyAsync(&total, W.lb_total.p, sizeof total, hipMemcpyDeviceToHost, st));
+          HIPCHK(hipStreamSynchronize(st));
+          if (total > nroots && total <= lb_cap) {
+            Node* out = W.lb_roots[pong].as<Node>();
+            HIPCHK(launch_zero_i32(W.err.as<int32_t>(), 1, st));
+            HIPCHK(launch_lb_emit(roots, nroots, W.lb_level.as<int32_t>(), W.lb_count.as<int32_t>(),
+                                  W.lb_off.as<int64_t>(), out,
+                                  W.hist.as<uint32_t>() + (size_t)i * kHistBins,
+                                  W.goal_g.as<int32_t>() + i, W.err.as<int32_t>(), st));
+            int32_t lb_err = 0;
+            HIPCHK(hipMemcpyAsync(&lb_err, W.err.p, sizeof lb_err, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (lb_err) {
+              code = BPIDA_EINTERNAL;
+              break;
+            }
+            stats[15] += (uint64_t)(total - nroots);
+            roots = out;
+            nroots = (int)total;
+            pong ^= 1;
+          }
         }
         L = R.fnext;
       }
@@ -919,6 +970,9 @@ extern "C" int bpida_set_option(const char* key, int64_t value) {
   } else if (k == "donate_every") {
     if (value < 4 || value > 1024 || (value & (value - 1))) return BPIDA_EINVAL;
     g_opt.donate_every = value;
+  } else if (k == "static_lb") {
+    if (value != 0 && value != 1) return BPIDA_EINVAL;
+    g_opt.static_lb = value;
   } else if (k == "first_solution") {
     if (value != 0 && value != 1) return BPIDA_EINVAL;
     g_opt.first_solution = value;
@@ -952,6 +1006,7 @@ extern "C" int64_t bpida_get_option(const char* key) {
   if (k == "donate_min") return g_opt.donate_min;
   if (k == "queue_chunk") return g_opt.queue_chunk;
   if (k == "first_solution") return g_opt.first_solution;
+  if (k == "static_lb") return g_opt.static_lb;
   return INT64_MIN;
 }
 

@@ -250,7 +250,17 @@ hipError_t launch_split4(const Inst* d_inst, int n, int depth, const int64_t* d_
                          hipStream_t s);
 hipError_t launch_search4(int lds_cap, int grid, const Node* d_roots, int nroots, int limit,
                           int32_t* d_cursor, uint64_t* d_spill_tiles, uint16_t* d_spill_meta,
-                          int spill_cap, Partial* d_part, int32_t* d_stop, hipStream_t s);
+                          int spill_cap, Partial* d_part, int32_t* d_stop, uint32_t* d_load,
+                          hipStream_t s);
+// Static load balancing of the plain path (bpida_lb.hip): plan (average
+// load, per-root split depth and size, offsets, total) and emit (the new
+// root list; interior nodes into the histogram and the interior-goal depth).
+hipError_t launch_lb_plan(const Node* d_roots, const uint32_t* d_load, int nroots, int limit,
+                          uint64_t* d_avg, int32_t* d_level, int32_t* d_count, int64_t* d_off,
+                          int64_t* d_total, hipStream_t s);
+hipError_t launch_lb_emit(const Node* d_roots, int nroots, const int32_t* d_level,
+                          const int32_t* d_count, const int64_t* d_off, Node* d_out,
+                          uint32_t* d_hist, int32_t* d_goal_g, int32_t* d_err, hipStream_t s);
 hipError_t launch_reduce(const Partial* d_part, int nwg, const uint32_t* d_hist_i,
                          const int32_t* d_goal_g_i, int limit, int col, uint64_t* d_nodes_row,
                          int32_t* d_cursor, LimitResult* d_res, hipStream_t s);

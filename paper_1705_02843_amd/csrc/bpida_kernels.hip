@@ -199,9 +199,12 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
                                                      uint64_t* __restrict__ spill_tiles,
                                                      uint16_t* __restrict__ spill_meta,
                                                      int spill_cap, Partial* __restrict__ part,
-                                                     int32_t* __restrict__ stop) {
+                                                     int32_t* __restrict__ stop,
+                                                     uint32_t* __restrict__ load) {
   // stop: null, or (first-solution mode) a flag the workgroup that expands a
-  // goal sets; the others see it within 64 rounds and drop their work
+  // goal sets; the others see it within 64 rounds and drop their work.
+  // load: null, or per root the repetitions of the round loop its subtree
+  // took (the work estimate of the static load balancing)
   static_assert((CAP & (CAP - 1)) == 0 && CAP >= 128, "ring size");
   __shared__ uint64_t st[CAP];
   __shared__ uint16_t sm[CAP];
@@ -236,6 +239,7 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
       sm[0] = (uint16_t)((R.meta & 0xFFu) | ((uint32_t)(limit - (int)R.f) << 8));
     }
     WAVE_SYNC();
+    const uint64_t rounds0 = rounds;
     uint32_t top = 1, bot = 0;  // unsigned ring positions: they wrap
     int sp = 0;
     for (;;) {
@@ -283,6 +287,7 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
         }
       }
     }
+    if (load && lane == 0) load[r] = (uint32_t)min<uint64_t>(rounds - rounds0, 0xFFFFFFFFull);
     if (stopped) break;
   }
   fmin = wave_min(fmin);
@@ -302,21 +307,22 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
 template <int CAP>
 static hipError_t launch_search4_t(int grid, const Node* d_roots, int nroots, int limit,
                                    int32_t* d_cursor, uint64_t* d_st, uint16_t* d_sm, int spill_cap,
-                                   Partial* d_part, int32_t* d_stop, hipStream_t s) {
+                                   Partial* d_part, int32_t* d_stop, uint32_t* d_load, hipStream_t s) {
   hipLaunchKernelGGL(search4_kernel<CAP>, dim3(grid), dim3(64), 0, s, d_roots, nroots, limit,
-                     d_cursor, d_st, d_sm, spill_cap, d_part, d_stop);
+                     d_cursor, d_st, d_sm, spill_cap, d_part, d_stop, d_load);
   return hipGetLastError();
 }
 
 hipError_t launch_search4(int lds_cap, int grid, const Node* d_roots, int nroots, int limit,
                           int32_t* d_cursor, uint64_t* d_spill_tiles, uint16_t* d_spill_meta,
-                          int spill_cap, Partial* d_part, int32_t* d_stop, hipStream_t s) {
+                          int spill_cap, Partial* d_part, int32_t* d_stop, uint32_t* d_load,
+                          hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   switch (lds_cap) {
 #define CASE(C)                                                                                 \
   case C:                                                                                       \
     return launch_search4_t<C>(grid, d_roots, nroots, limit, d_cursor, d_spill_tiles,           \
-                               d_spill_meta, spill_cap, d_part, d_stop, s);
+                               d_spill_meta, spill_cap, d_part, d_stop, d_load, s);
     CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048)
 #undef CASE
     default:

@@ -32,7 +32,7 @@ def B():
 
 OPTION_KEYS = ("mode", "frontier_depth", "lds_stack_capacity", "spill_capacity",
                "max_workgroups", "max_threshold", "queue_capacity", "watchdog_ms",
-               "nodes_per_round", "budget_ms", "first_solution")
+               "nodes_per_round", "budget_ms", "first_solution", "static_lb")
 # plain: one launch per instance and limit, 16-node rounds (Alg. 1's map);
 # batched: persistent launch, 64-node rounds; batched16: persistent, 16-node
 MODES = {"plain": {"mode": 0}, "batched": {"mode": 1, "nodes_per_round": 64},
@@ -307,3 +307,38 @@ def test_c3_4096_batched_exact_where_stored_and_valid_everywhere(opts):
         row = nodes[i, :ncols[i]]
         assert (np.diff(row.astype(np.int64)) > 0).all()
     _say("c3 stats: %s" % B.last_stats())
+
+
+@pytest.mark.parametrize("lb", [0, 1])
+def test_plain_static_load_balancing_exact(opts, lb):
+    """Plain BPIDA* with and without its static load balancing (Sec. 5): the
+    re-split root sets expand exactly the oracle's nodes at every limit."""
+    B = opts
+    _say("case: plain, static_lb=%d, c1_walk40 + first 30 of c2_md30_38" % lb)
+    set_mode(B, "plain")
+    B.set_option("static_lb", lb)
+    for name, k in (("c1_walk40", 64), ("c2_md30_38", 30)):
+        states, length, nodes = load_golden(name)
+        rc, ln, got = B.solve_raw(states[:k])
+        assert rc == B.OK, B.strerror(rc)
+        assert_parity(ln, got, length[:k], nodes[:k], "%s lb=%d" % (name, lb))
+        added = B.last_stats()["lb_roots_added"]
+        if lb == 0:
+            assert added == 0
+        elif name == "c2_md30_38":
+            assert added > 0, "no root was re-split"
+
+
+def test_plain_static_lb_small_split_depth(opts):
+    """Re-splitting from a shallow split (D = 2, a handful of roots) goes
+    several levels deep within one instance; counts stay exact."""
+    B = opts
+    _say("case: plain, static_lb=1, split depth 2")
+    set_mode(B, "plain")
+    B.set_option("static_lb", 1)
+    B.set_option("frontier_depth", 2)
+    states, length, nodes = load_golden("c2_md30_38")
+    rc, ln, got = B.solve_raw(states[:12])
+    assert rc == B.OK, B.strerror(rc)
+    assert_parity(ln, got, length[:12], nodes[:12], "D=2 lb")
+    assert B.last_stats()["lb_roots_added"] > 0
