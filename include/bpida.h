@@ -212,6 +212,11 @@ int bpida_server_stop(void);
  *   "donate_every"       batched mode: rounds between a workgroup's checks
  *                        for waiting workgroups to donate to (a power of
  *                        two in 4..1024, default 128)
+ *   "start_threshold"    first f-limit to search: -1 (default) = h0; else the
+ *                        smallest h0 + 2j >= the value.  Columns of skipped
+ *                        limits stay 0.  out_len is then the first searched
+ *                        limit that holds a goal: the optimal length only if
+ *                        the start does not exceed it.
  *   "static_lb"          plain mode: 1 (default) re-splits, between limits, every
  *                        root whose repetition count exceeded the average of
  *                        the searched roots (Sec. 5, BPIDA*'s static load

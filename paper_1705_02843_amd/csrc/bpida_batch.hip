@@ -445,8 +445,8 @@ __device__ void admitter_loop(const BatchArgs& A, uint64_t* st, uint16_t* sm, ui
     A.out_nodes[(size_t)slot * 64 + lane] = 0;
     if (lane == 0) A.out_len[slot] = -1;
     InstState S;
-    S.limit = I.h0;
-    S.col = 0;
+    S.limit = first_limit(I.h0, A.start_limit);
+    S.col = (S.limit - I.h0) / 2;
     S.done = I.status;
     S.outstanding = 0;
     S.nodes = 0;
@@ -759,8 +759,8 @@ __global__ void batch_setup_kernel(BatchArgs A, const InstW* __restrict__ inst,
   if (k <= (int64_t)A.qmask) A.seq[k] = (uint64_t)k;
   if (k < A.n) {
     InstState S;
-    S.limit = inst[k].h0;
-    S.col = 0;
+    S.limit = first_limit(inst[k].h0, A.start_limit);
+    S.col = (S.limit - inst[k].h0) / 2;
     S.done = inst[k].status;  // 0 = to search
     S.outstanding = 0;
     S.nodes = 0;
@@ -770,7 +770,7 @@ __global__ void batch_setup_kernel(BatchArgs A, const InstW* __restrict__ inst,
     S.root_off = root_off[k];
     S.nroots = nroots[k];
     S.width = inst[k].width;
-    if (S.done == 0 && S.limit > A.max_limit) S.done = -3;  // BPIDA_ELIMIT
+    if (S.done == 0 && (S.limit > A.max_limit || S.col >= 64)) S.done = -3;  // BPIDA_ELIMIT
     A.is[k] = S;
     if (S.done == 0) atomicAdd(&A.q->remaining, 1);
   }

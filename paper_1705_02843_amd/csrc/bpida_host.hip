@@ -40,6 +40,7 @@ struct Options {
   int64_t queue_chunk = 64;    // batched mode: entries per donated chunk (16, 32 or 64)
   int64_t first_solution = 0;  // 1: the final limit stops at its first goal (Alg. 1 as printed)
   int64_t static_lb = 1;       // plain mode: re-split heavy roots between limits (Sec. 5)
+  int64_t start_threshold = -1; // first f-limit to search (-1: h0)
 };
 
 std::mutex g_mu;  // serialises solves and option changes
@@ -274,9 +275,9 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
       int nroots = lc[(size_t)i * L1 + D];
       const Node* roots = W.tree.as<Node>() + root_off[i];
       int pong = 0;
-      int L = inst[i].h0;
+      int L = first_limit(inst[i].h0, (int)O.start_threshold);
       code = BPIDA_ELIMIT;
-      for (int j = 0; j < BPIDA_MAX_THRESHOLDS; ++j) {
+      for (int j = (L - inst[i].h0) / 2; j < BPIDA_MAX_THRESHOLDS; ++j) {
         if (L > kMaxLimit || (O.max_threshold >= 0 && L > O.max_threshold)) break;
         const int grid = (int)std::min<int64_t>(nroots, max_grid);
         uint32_t* load = nullptr;
@@ -496,6 +497,7 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
   A.donate_min = (int32_t)O.donate_min;
   A.donate_window = 2 * (int32_t)O.queue_chunk;
   A.first_solution = (int32_t)O.first_solution;
+  A.start_limit = (int32_t)O.start_threshold;
   HIPCHK(launch_batch_setup(A, W.winst.as<InstW>(), W.root_off.as<int64_t>(), W.nroots.as<int32_t>(), st));
   if (timed) HIPCHK(hipEventRecord(W.ev0, st));
   HIPCHK(launch_batch4(cap, npl, (int)grid, A, st));
@@ -804,6 +806,7 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     A.donate_min = (int32_t)O.donate_min;
     A.donate_window = 2 * (int32_t)O.queue_chunk;
     A.first_solution = (int32_t)O.first_solution;
+    A.start_limit = (int32_t)O.start_threshold;
     A.server = 1;
     A.srv.host = V.host;
     A.srv.req = V.req;
@@ -970,6 +973,9 @@ extern "C" int bpida_set_option(const char* key, int64_t value) {
   } else if (k == "donate_every") {
     if (value < 4 || value > 1024 || (value & (value - 1))) return BPIDA_EINVAL;
     g_opt.donate_every = value;
+  } else if (k == "start_threshold") {
+    if (value < -1 || value > kMaxLimit) return BPIDA_EINVAL;
+    g_opt.start_threshold = value;
   } else if (k == "static_lb") {
     if (value != 0 && value != 1) return BPIDA_EINVAL;
     g_opt.static_lb = value;
@@ -1007,6 +1013,7 @@ extern "C" int64_t bpida_get_option(const char* key) {
   if (k == "queue_chunk") return g_opt.queue_chunk;
   if (k == "first_solution") return g_opt.first_solution;
   if (k == "static_lb") return g_opt.static_lb;
+  if (k == "start_threshold") return g_opt.start_threshold;
   return INT64_MIN;
 }
 

@@ -63,6 +63,12 @@ struct alignas(16) Node {
   uint32_t f;  // g + h
 };
 
+// The first f-limit searched: h0, or the smallest h0 + 2j >= start when the
+// caller asks to start higher (start < 0: h0).
+__host__ __device__ inline int first_limit(int h0, int start) {
+  return start <= h0 ? h0 : h0 + ((start - h0 + 1) & ~1);
+}
+
 __host__ __device__ inline uint32_t node_meta(int blank, int forbid, int g, int h) {
   return (uint32_t)blank | ((uint32_t)forbid << 5) | ((uint32_t)g << 8) | ((uint32_t)h << 16);
 }
@@ -223,6 +229,7 @@ struct BatchArgs {
   int32_t donate_min;    // only stacks of at least this many entries donate (<= 0: 4 rounds of pops, <= ring / 2)
   int32_t donate_window; // a donation splits the oldest min(window, stack) entries (2 x chunk)
   int32_t first_solution; // nonzero: the final limit stops at its first goal
+  int32_t start_limit;    // first f-limit to search (< 0: h0)
   int32_t server;        // nonzero: continuous-batching server (srv below)
   ServerArgs srv;
 };

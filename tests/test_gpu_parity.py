@@ -32,7 +32,7 @@ def B():
 
 OPTION_KEYS = ("mode", "frontier_depth", "lds_stack_capacity", "spill_capacity",
                "max_workgroups", "max_threshold", "queue_capacity", "watchdog_ms",
-               "nodes_per_round", "budget_ms", "first_solution", "static_lb")
+               "nodes_per_round", "budget_ms", "first_solution", "static_lb", "start_threshold")
 # plain: one launch per instance and limit, 16-node rounds (Alg. 1's map);
 # batched: persistent launch, 64-node rounds; batched16: persistent, 16-node
 MODES = {"plain": {"mode": 0}, "batched": {"mode": 1, "nodes_per_round": 64},
@@ -342,3 +342,26 @@ def test_plain_static_lb_small_split_depth(opts):
     assert rc == B.OK, B.strerror(rc)
     assert_parity(ln, got, length[:12], nodes[:12], "D=2 lb")
     assert B.last_stats()["lb_roots_added"] > 0
+
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_start_threshold_at_the_optimum(opts, mode):
+    """Starting at the optimal length (or one below it: rounded up to h0's
+    parity) runs only the final limit: its count is the stored one, the
+    skipped columns stay zero."""
+    B = opts
+    _say("case: start_threshold = optimum, c1_walk40, %s" % mode)
+    set_mode(B, mode)
+    states, length, nodes = load_golden("c1_walk40")
+    try:
+        for delta in (0, -1):
+            for i in (3, 17, 40):
+                B.set_option("start_threshold", int(length[i]) + delta)
+                rc, ln, got = B.solve_raw(states[i:i + 1])
+                assert rc == B.OK, B.strerror(rc)
+                k = int(np.count_nonzero(nodes[i]))
+                assert ln[0] == length[i]
+                assert got[0, k - 1] == nodes[i, k - 1] and not got[0, :k - 1].any()
+                assert not got[0, k:].any()
+    finally:
+        B.set_option("start_threshold", -1)
