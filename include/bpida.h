@@ -232,6 +232,8 @@ int bpida_server_stop(void);
  *                        holds the nodes expanded before the search stopped
  *                        (at most the all-solutions count, and it varies
  *                        from run to run).
+ *   "seed_chunk"         batched mode: roots per chunk when a limit is seeded
+ *                        into the work queue: 8, 16, 32 or 64 (default)
  *   "queue_chunk"        batched mode: entries per donated chunk, 16, 32 or
  *                        64 (default); a donation splits the oldest
  *                        2 x queue_chunk entries of the donor's stack

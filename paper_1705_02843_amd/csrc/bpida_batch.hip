@@ -170,18 +170,24 @@ __device__ bool seed_limit(const BatchArgs& A, int i, uint64_t* stage, uint16_t*
       stage_m[off] = stack_meta((int)(R.meta & 31u), (int)((R.meta >> 5) & 7u), L - (int)R.f);
     }
     WAVE_SYNC();
-    const uint64_t t = stage[lane];
-    const uint64_t th = stage[64 + lane];
-    const uint16_t m = stage_m[lane];
-    WAVE_SYNC();
-    if (lane == 0) __hip_atomic_fetch_add(&S->outstanding, 1, __ATOMIC_RELAXED, AGENT);
-    if (!q_push(A, t, th, m, cnt, i, wide)) {
-      full = true;  // the remaining roots are dropped; the call reports BPIDA_ENOMEM
-      if (lane == 0) {
-        __hip_atomic_fetch_add(&S->outstanding, -1, __ATOMIC_RELAXED, AGENT);
-        atomicOr(&A.q->err, 1);
+    // chunks of seed_chunk roots: smaller seeds when a batch has few roots
+    // per workgroup, so the whole grid has work from the start
+    const int sc = A.seed_chunk > 0 ? A.seed_chunk : kQChunk;
+    for (int p0 = 0; p0 < cnt && !full; p0 += sc) {
+      const int pc = min(sc, cnt - p0);
+      const uint64_t t = lane < pc ? stage[p0 + lane] : 0ull;
+      const uint64_t th = lane < pc ? stage[64 + p0 + lane] : 0ull;
+      const uint16_t m = lane < pc ? stage_m[p0 + lane] : (uint16_t)0;
+      if (lane == 0) __hip_atomic_fetch_add(&S->outstanding, 1, __ATOMIC_RELAXED, AGENT);
+      if (!q_push(A, t, th, m, pc, i, wide)) {
+        full = true;  // the remaining roots are dropped; the call reports BPIDA_ENOMEM
+        if (lane == 0) {
+          __hip_atomic_fetch_add(&S->outstanding, -1, __ATOMIC_RELAXED, AGENT);
+          atomicOr(&A.q->err, 1);
+        }
       }
     }
+    WAVE_SYNC();
   }
   fm = wave_min(fm);
   int last = 0;

@@ -41,6 +41,7 @@ struct Options {
   int64_t first_solution = 0;  // 1: the final limit stops at its first goal (Alg. 1 as printed)
   int64_t static_lb = 1;       // plain mode: re-split heavy roots between limits (Sec. 5)
   int64_t start_threshold = -1; // first f-limit to search (-1: h0)
+  int64_t seed_chunk = 64;      // batched mode: roots per seeded chunk (8, 16, 32, 64)
 };
 
 std::mutex g_mu;  // serialises solves and option changes
@@ -462,10 +463,15 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
   if (O.max_workgroups > 0) grid = std::min<int64_t>(grid, O.max_workgroups);
   uint64_t qcap = 64;
   // Default size: the seeds plus, per workgroup, room for the chunks its
-  // ring overflows into.  A 5x5 subtree's stack runs deeper and its ring
-  // holds half as many entries, so it spills several times more (measured
-  // peaks: about 6 chunks per workgroup for 4x4 batches, 36 for 5x5).
-  const int64_t per_wg = any5 ? 64 : 16;
+  // ring overflows into.  Smaller rings spill more (64-node rounds on a
+  // 512-entry ring spill ~10x more than on 1024), and a 5x5 subtree's stack
+  // runs deeper on a ring of half as many entries (measured peaks: about 6
+  // chunks per workgroup for 4x4 batches on 1024 entries, 36 for 5x5).
+  // Smaller seed chunks were measured not to help (the grid fills through
+  // donation within the first rounds), so 64 is the default.
+  const int sc = (int)O.seed_chunk;
+  seed_chunks *= kQChunk / sc;
+  const int64_t per_wg = any5 ? 64 : std::min<int64_t>(64, std::max<int64_t>(16, 32768 / cap));
   const uint64_t want = O.queue_capacity > 0 ? (uint64_t)O.queue_capacity
                                               : (uint64_t)(seed_chunks + grid * per_wg + 1024);
   while (qcap < want) qcap <<= 1;
@@ -498,6 +504,7 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
   A.donate_window = 2 * (int32_t)O.queue_chunk;
   A.first_solution = (int32_t)O.first_solution;
   A.start_limit = (int32_t)O.start_threshold;
+  A.seed_chunk = sc;
   HIPCHK(launch_batch_setup(A, W.winst.as<InstW>(), W.root_off.as<int64_t>(), W.nroots.as<int32_t>(), st));
   if (timed) HIPCHK(hipEventRecord(W.ev0, st));
   HIPCHK(launch_batch4(cap, npl, (int)grid, A, st));
@@ -745,10 +752,11 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     const int64_t S = max_inflight;
     uint64_t ring = 64;
     while (ring < (uint64_t)ring_capacity) ring <<= 1;
+    const int sc_srv = (int)O.seed_chunk;
     uint64_t qcap = 64;
     const uint64_t want = O.queue_capacity > 0
                               ? (uint64_t)O.queue_capacity
-                              : (uint64_t)(S * ((max_roots + kQChunk - 1) / kQChunk) + grid * 16 + 1024);
+                              : (uint64_t)(S * ((max_roots + sc_srv - 1) / sc_srv) + grid * 32 + 1024);
     while (qcap < want) qcap <<= 1;
     free_server_host(V);
     if (V.qctl.ensure(sizeof(QueueCtl)) != hipSuccess || V.qseq.ensure(sizeof(uint64_t) * qcap) != hipSuccess ||
@@ -807,6 +815,7 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     A.donate_window = 2 * (int32_t)O.queue_chunk;
     A.first_solution = (int32_t)O.first_solution;
     A.start_limit = (int32_t)O.start_threshold;
+    A.seed_chunk = sc_srv;
     A.server = 1;
     A.srv.host = V.host;
     A.srv.req = V.req;
@@ -973,6 +982,9 @@ extern "C" int bpida_set_option(const char* key, int64_t value) {
   } else if (k == "donate_every") {
     if (value < 4 || value > 1024 || (value & (value - 1))) return BPIDA_EINVAL;
     g_opt.donate_every = value;
+  } else if (k == "seed_chunk") {
+    if (value != 8 && value != 16 && value != 32 && value != 64) return BPIDA_EINVAL;
+    g_opt.seed_chunk = value;
   } else if (k == "start_threshold") {
     if (value < -1 || value > kMaxLimit) return BPIDA_EINVAL;
     g_opt.start_threshold = value;
@@ -1014,6 +1026,7 @@ extern "C" int64_t bpida_get_option(const char* key) {
   if (k == "first_solution") return g_opt.first_solution;
   if (k == "static_lb") return g_opt.static_lb;
   if (k == "start_threshold") return g_opt.start_threshold;
+  if (k == "seed_chunk") return g_opt.seed_chunk;
   return INT64_MIN;
 }
 

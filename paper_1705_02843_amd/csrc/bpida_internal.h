@@ -230,6 +230,7 @@ struct BatchArgs {
   int32_t donate_window; // a donation splits the oldest min(window, stack) entries (2 x chunk)
   int32_t first_solution; // nonzero: the final limit stops at its first goal
   int32_t start_limit;    // first f-limit to search (< 0: h0)
+  int32_t seed_chunk;     // roots per seeded chunk (8..64)
   int32_t server;        // nonzero: continuous-batching server (srv below)
   ServerArgs srv;
 };

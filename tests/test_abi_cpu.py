@@ -74,7 +74,7 @@ def test_options_roundtrip_and_validation(B):
     for k, v in (("frontier_depth", 17), ("frontier_depth", -2), ("lds_stack_capacity", 300), ("mode", 2), ("nodes_per_round", 32),
                  ("queue_capacity", -1), ("watchdog_ms", 0),
                  ("spill_capacity", 65), ("max_threshold", -2), ("donate_every", 48),
-                 ("donate_every", 2), ("donate_min", 0), ("donate_min", 4096), ("queue_chunk", 48), ("start_threshold", -2),
+                 ("donate_every", 2), ("donate_min", 0), ("donate_min", 4096), ("queue_chunk", 48), ("start_threshold", -2), ("seed_chunk", 12), ("seed_chunk", -1),
                  ("static_lb", 2), ("first_solution", 2), ("no_such_key", 1)):
         with pytest.raises(B.BpidaError):
             B.set_option(k, v)

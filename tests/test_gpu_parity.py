@@ -32,7 +32,8 @@ def B():
 
 OPTION_KEYS = ("mode", "frontier_depth", "lds_stack_capacity", "spill_capacity",
                "max_workgroups", "max_threshold", "queue_capacity", "watchdog_ms",
-               "nodes_per_round", "budget_ms", "first_solution", "static_lb", "start_threshold")
+               "nodes_per_round", "budget_ms", "first_solution", "static_lb", "start_threshold",
+               "seed_chunk")
 # plain: one launch per instance and limit, 16-node rounds (Alg. 1's map);
 # batched: persistent launch, 64-node rounds; batched16: persistent, 16-node
 MODES = {"plain": {"mode": 0}, "batched": {"mode": 1, "nodes_per_round": 64},
@@ -365,3 +366,18 @@ def test_start_threshold_at_the_optimum(opts, mode):
                 assert not got[0, k:].any()
     finally:
         B.set_option("start_threshold", -1)
+
+
+@pytest.mark.parametrize("sc", [8, 16])
+def test_batched_small_seed_chunks_exact(opts, sc):
+    """Seeding a limit in chunks of fewer than 64 roots (several queue pushes
+    per 64 candidate roots) leaves every count unchanged."""
+    B = opts
+    _say("case: batched, seed_chunk=%d, c1_walk40 + first 20 of c2_md30_38" % sc)
+    set_mode(B, "batched")
+    B.set_option("seed_chunk", sc)
+    for name, k in (("c1_walk40", 64), ("c2_md30_38", 20)):
+        states, length, nodes = load_golden(name)
+        rc, ln, got = B.solve_raw(states[:k])
+        assert rc == B.OK, B.strerror(rc)
+        assert_parity(ln, got, length[:k], nodes[:k], "%s seed_chunk=%d" % (name, sc))
