@@ -381,3 +381,20 @@ def test_batched_small_seed_chunks_exact(opts, sc):
         rc, ln, got = B.solve_raw(states[:k])
         assert rc == B.OK, B.strerror(rc)
         assert_parity(ln, got, length[:k], nodes[:k], "%s seed_chunk=%d" % (name, sc))
+
+
+def test_batched_100k_cheap_instances_exact(opts):
+    """A batch far larger than the grid (100,000 states from walks of 0..30
+    moves, split tree and queue sized from the batch): exact against the
+    oracle run live on the same states."""
+    B = opts
+    from paper_1705_02843_amd import instances as I
+    rng = np.random.Generator(np.random.PCG64(77))
+    states = np.stack([I.random_walk(rng, 4, int(k))[0] for k in rng.integers(0, 31, size=100000)])
+    want = oracle_expect(states)
+    assert want.rc == 0
+    _say("case: batched, 100000 cheap states in one launch")
+    set_mode(B, "batched")
+    rc, ln, got = B.solve_raw(states)
+    assert rc == B.OK, B.strerror(rc)
+    assert_parity(ln, got, want.length, want.nodes, "100k")
