@@ -155,7 +155,7 @@ def main():
         if args.n:
             states = states[:args.n]
         n = states.shape[0]
-    res = tune(states, width, args.reps if n <= 2048 else 0, widths=widths)
+    res = tune(states, width, args.reps if n <= 2048 else 1, widths=widths)
     table = {}
     if os.path.exists(args.out):
         with open(args.out) as f:
