@@ -229,11 +229,16 @@ def main():
     ap.add_argument("--untuned", action="store_true",
                     help="ignore the autotuner's table (paper_1705_02843_amd/tuning/) and use the "
                          "library defaults")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only the timed steps (no comparison, host-buffer, first-solution or CPU "
+                         "legs): for profiling runs")
     ap.add_argument("--no-first-solution", action="store_true",
                     help="skip the first-solution leg (final limit stops at its first goal)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
+    if args.kernel_only:
+        args.no_compare = args.no_first_solution = args.no_cpu_baseline = True
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
@@ -390,7 +395,7 @@ def main():
                           "instances_per_s": round(n / odt, 2), "steps": 1, "warmup": 1,
                           "speedup_of_value": round((nodes_per_step / odt) and value / (nodes_per_step / odt), 3)}
         bpida.set_option("mode", MODES[args.mode])
-    if args.mode == "batched":
+    if args.mode == "batched" and not args.kernel_only:
         # the host-buffer entry (PCIe copies in and out included), beside `value`
         ts = []
         for _ in range(3):
