@@ -79,3 +79,18 @@ def test_first_solution_mixed_widths(opts):
     assert rc == B.OK, B.strerror(rc)
     check_first_solution(ln[:64], got[:64], a3.length, a3.nodes, "3x3")
     check_first_solution(ln[64:], got[64:], a4.length, a4.nodes, "4x4")
+
+
+def test_first_solution_plain_with_static_lb(opts):
+    B = opts
+    _say("case: first solution, plain with static load balancing, c2_md30_38 (first 20)")
+    set_mode(B, "plain")
+    B.set_option("static_lb", 1)
+    states, length, nodes = load_golden("c2_md30_38")
+    B.set_option("first_solution", 1)
+    try:
+        rc, ln, got = B.solve_raw(states[:20])
+    finally:
+        B.set_option("first_solution", 0)
+    assert rc == B.OK, B.strerror(rc)
+    check_first_solution(ln, got, length[:20], nodes[:20], "plain+lb")

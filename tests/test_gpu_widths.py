@@ -154,3 +154,31 @@ def test_c4_mixed_one_launch_exact_and_same_as_alone(B):
             h0 = np.array([I.manhattan_filter_value(x, w) for x in s])
             assert (ln[off:off + k] >= h0).all() and ((ln[off:off + k] - h0) % 2 == 0).all()
         off += k
+
+
+def test_mixed_batch_with_bad_states(B):
+    """Invalid and unsolvable boards of every width inside one mixed batch:
+    each gets its own status (-1 length, zero counts), the first failing code
+    is returned, and every other instance is still exact."""
+    from paper_1705_02843_amd import instances as I
+    print("case: mixed batch with invalid and unsolvable boards", flush=True)
+    d = I.c4_mixed(n3=8, n4=8, n5=1)
+    s3 = list(d[3][0])
+    s4 = [s for s in d[4][0] if I.manhattan_filter_value(s, 4) <= 30][:4]
+    s5 = five_by_five_states(4)[:4]
+    bad3 = np.arange(9, dtype=np.uint8)[[0, 2, 1, 3, 4, 5, 6, 7, 8]]   # two tiles swapped: wrong parity
+    bad4 = np.zeros(16, np.uint8)                                      # not a permutation
+    bad5 = np.arange(25, dtype=np.uint8)[[0, 2, 1] + list(range(3, 25))]  # two tiles swapped
+    items = [bad3] + s3 + [bad4] + s4 + s5 + [bad5]
+    rc, ln, nodes = B.solve_mixed_raw(items)
+    assert rc in (B.EUNSOLVABLE, B.EINVAL)
+    bad = {0, 1 + len(s3), len(items) - 1}
+    for k in bad:
+        assert ln[k] == -1 and not nodes[k].any(), k
+    good = [k for k in range(len(items)) if k not in bad]
+    ws = [int(round(len(items[k]) ** 0.5)) for k in good]
+    for w in (3, 4, 5):
+        ks = [k for k, ww in zip(good, ws) if ww == w]
+        want = oracle_of([items[k] for k in ks], w)
+        for j, k in enumerate(ks):
+            assert ln[k] == want.length[j] and (nodes[k] == want.nodes[j]).all(), (w, k)
