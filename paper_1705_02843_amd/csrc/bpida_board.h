@@ -201,8 +201,9 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
   constexpr bool vert = A == 0 || A == 3;
   constexpr uint32_t K = vert ? ((1u << (B::BITS * W)) - 1u) : B::MASK;
   // shift to the neighbour's cell; it wraps (and the tile is unused) when
-  // the move is illegal
-  const uint32_t sh_n = (c.shb + (uint32_t)(B::BITS * delta)) & (8u * sizeof(S) - 1u);
+  // the move is illegal, and needs no mask on a legal one
+  const uint32_t shu = c.shb + (uint32_t)(B::BITS * delta);
+  const uint32_t sh_n = shu & (8u * sizeof(S) - 1u);
   const uint32_t x = (uint32_t)(s >> sh_n);  // tile t in the low BITS bits
   const uint32_t up = B::template up<A>(x, c.rowi, c.coli);
   upm |= up << A;
@@ -211,11 +212,10 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
   if (kb != 0u) {
     // successor: t moves from n to b, i.e. the packed word changes by
     // t * (base^b - base^n) = +/- (K * t) << (BITS * min(b, n))
-    // (on a legal move the neighbour's shift is in range without the mask)
     uint32_t kt;
     if constexpr (K < (1u << 24)) kt = mul_u24(K, x & B::MASK);
     else kt = K * (x & B::MASK);  // 5x5 rows: K = 2^25 - 1
-    const S d = (S)kt << (A < 2 ? c.shb + (uint32_t)(B::BITS * delta) : c.shb);
+    const S d = (S)kt << (A < 2 ? shu : c.shb);
     const S cs = A < 2 ? s + d : s - d;
     // stack meta: n | (3 - A) << 5 | (slack - 2 up) << 8
     const uint32_t cm = mad_i24(up, -512, c.mbase) + (uint32_t)(delta + ((3 - A) << 5));
