@@ -7,8 +7,10 @@
  * puzzle with the Manhattan distance heuristic (Sec. 1, Sec. 3).  All search
  * work runs in HIP kernels: ingest (validate, pack, h), root split
  * (CreateRootSet), the block-parallel f-limited DFS (BPDFS: one subtree per
- * workgroup, the DFS stack in LDS, one wavefront expanding 16 nodes x 4 moves
- * per round) and the per-limit reduction of node counts and next limits.
+ * workgroup, the DFS stack in LDS, one wavefront expanding per round either
+ * 16 nodes x 4 moves, Alg. 1's thread-to-action map, or 64 nodes, one per
+ * lane with its four moves, the batched default) and the per-limit reduction
+ * of node counts and next limits.
  *
  * Conventions shared by every entry point:
  *   - a state is width*width bytes, row-major; byte p is the tile at cell p,
@@ -19,7 +21,8 @@
  *   - the f-limits are h0, h0+2, ... (Manhattan changes by exactly 1 per
  *     move and keeps the parity of the path length, so no other limit can
  *     occur); the final limit, the optimal length, is searched to completion
- *     so that every count is unique.
+ *     so that every count is unique (unless the first_solution option asks
+ *     for Alg. 1's stop at the first goal).
  *
  * Thread safety: calls may come from several host threads; they are
  * serialised inside the library (one shared device workspace per device).
@@ -50,8 +53,8 @@ enum bpida_status {
   BPIDA_ELIMIT = -3,      /* more than BPIDA_MAX_THRESHOLDS limits, or past the
                              max_threshold option; counts of the limits that
                              were completed are kept                            */
-  BPIDA_ENOMEM = -4,      /* device allocation failed, or a per-workgroup spill
-                             area overflowed                                    */
+  BPIDA_ENOMEM = -4,      /* device allocation failed, a per-workgroup spill
+                             area (plain) or the work queue (batched) overflowed */
   BPIDA_EDEVICE = -5,     /* no usable gfx950 device, or a HIP call failed      */
   BPIDA_EINTERNAL = -6,   /* a consistency check failed (next limit != L + 2),
                              or a persistent launch stopped by its watchdog or
@@ -109,7 +112,8 @@ int bpida_solve_mixed_device(const uint8_t *d_states, const int32_t *widths, int
  * per-instance status is written to d_len (-1) and the return value is the
  * first failing code.  Work is ordered on `hip_stream` (a hipStream_t, NULL =
  * the null stream); the call returns after the results are in d_len and
- * d_nodes (the limit loop reads 16 bytes per limit back to the host).
+ * d_nodes (plain mode: the limit loop reads 16 bytes per limit back to the
+ * host; batched mode: one read of the per-instance status after the launch).
  */
 int bpida_solve_device(const uint8_t *d_states, int32_t n_instances, int32_t width,
                        int32_t *d_len, uint64_t *d_nodes, void *hip_stream);
