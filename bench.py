@@ -229,6 +229,8 @@ def main():
     ap.add_argument("--untuned", action="store_true",
                     help="ignore the autotuner's table (paper_1705_02843_amd/tuning/) and use the "
                          "library defaults")
+    ap.add_argument("--no-static-lb", action="store_true",
+                    help="plain mode without BPIDA*'s static load balancing (Sec. 5)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the timed steps (no comparison, host-buffer, first-solution or CPU "
                          "legs): for profiling runs")
@@ -281,6 +283,8 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
+
+    bpida.set_option("static_lb", 0 if args.no_static_lb else 1)
 
     def run_mode(mode, steps, warmup):
         bpida.set_option("mode", MODES[mode])
