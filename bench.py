@@ -200,8 +200,9 @@ def first_solution_leg(bpida, part, states, width, d_states, d_len, d_nodes, str
 
 
 def load_traffic(src_hash, mode, workload):
-    """Per-launch HBM bytes of the timed search kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    """The committed rocprofv3 counter record of the timed search kernel (HBM
+    bytes per launch, VALU busy, active lanes), if it was taken on the
+    current kernel source."""
     path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (
         "batch4" if mode == "batched" else "search4", workload))
     if not os.path.exists(path):
@@ -210,7 +211,7 @@ def load_traffic(src_hash, mode, workload):
         t = json.load(f)
     if t.get("kernel_source_hash") != src_hash:
         return None
-    return t.get("bytes_per_launch")
+    return t
 
 
 def main():
@@ -332,7 +333,8 @@ def main():
     ops_per_launch = search_nodes * OPS_PER_NODE / launches if launches else 0.0
     achieved = ops_per_launch / avg_launch_s / 1e9 if launches else 0.0
     src_hash = kernel_source_hash()
-    traffic = load_traffic(src_hash, args.mode, args.workload)
+    counters = load_traffic(src_hash, args.mode, args.workload)
+    traffic = counters.get("bytes_per_launch") if counters else None
     npl = bpida.get_option("nodes_per_round") if args.mode == "batched" else 16
     cap = bpida.get_option("lds_stack_capacity")
     if cap < 0:
@@ -376,6 +378,10 @@ def main():
                      "launches_per_step": launches // max(1, args.steps),
                      "search_nodes_per_s_in_kernel": round(search_nodes / (search_us * 1e-6), 1)
                      if search_us else None},
+        "counters": ({k: counters[k] for k in ("valu_busy_frac", "active_lanes_frac",
+                                                "valu_instructions_per_node",
+                                                "lds_bank_conflict_cycles", "waves_per_simd")
+                      if k in counters} if counters else None),
         "search_rounds_per_step": rounds // max(1, args.steps),
         "pop_occupancy": round(search_nodes / (16.0 * rounds), 4) if rounds else None,
         "kernel_source_hash": src_hash,
