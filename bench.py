@@ -51,10 +51,16 @@ MIXED_PARTS = (("c4_mixed_w3", 3), ("c4_mixed_w4", 4), ("c4_mixed_w5", 5))
 MODES = {"plain": 0, "batched": 1}
 
 
+# The device sources the search kernels are built from (host-side driver
+# code does not change what a kernel launch moves or executes).
+DEVICE_SOURCES = ("bpida_batch.hip", "bpida_board.h", "bpida_internal.h", "bpida_kernels.hip",
+                  "bpida_lb.hip", "bpida_round.h")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1705_02843_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
+    for fn in DEVICE_SOURCES:
         with open(os.path.join(csrc, fn), "rb") as f:
             h.update(fn.encode() + f.read())
     return h.hexdigest()[:16]

@@ -323,6 +323,8 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
           code = BPIDA_EINTERNAL;
           break;
         }
+        // (every limit, small ones included: the re-splits compound, each
+        // refining the root set the next, larger limits inherit)
         if (O.static_lb && nroots > 0) {
           // Sec. 5: re-split the roots whose repetition count exceeded the
           // average, for the next iteration
