@@ -115,6 +115,9 @@ def solve_mixed_raw(states_list):
     """Batch of states of mixed widths (a list of uint8 vectors of w*w
     entries).  Returns (rc, out_len int32[n], nodes uint64[n, 64])."""
     widths = np.array([int(round(len(s) ** 0.5)) for s in states_list], np.int32)
+    for k, (s, w) in enumerate(zip(states_list, widths)):
+        if len(s) != int(w) * int(w):
+            raise ValueError("state %d has %d entries, not a square board" % (k, len(s)))
     flat = np.ascontiguousarray(np.concatenate([np.asarray(s, np.uint8).reshape(-1)
                                                 for s in states_list]) if states_list
                                 else np.zeros(0, np.uint8))

@@ -90,3 +90,9 @@ def test_strerror_covers_codes(B):
 def test_last_stats_shape(B):
     s = B.last_stats()
     assert set(s) >= {"rounds", "search_nodes", "spilled", "launches", "search_us"}
+
+
+def test_mixed_binding_rejects_non_square_states(B):
+    import numpy as np
+    with pytest.raises(ValueError):
+        B.solve_mixed_raw([np.arange(9, dtype=np.uint8), np.arange(10, dtype=np.uint8)])
