@@ -274,7 +274,7 @@ int64_t bpida_get_option(const char *key);
  *   out[12] batched mode: workgroups in the persistent grid
  *   out[13] batched mode: error bits (1 queue full while seeding, 2 entries
  *          dropped, 4 idle watchdog, 8 deadline, 16 queue ring full,
- *          256 split check)
+ *          32 LDS stack overrun, 256 split check)
  *   out[14] batched mode: work-queue slots (chunks of 64 entries)
  *   out[15] plain mode: roots added by the static load balancing
  * n = number of slots to fill (<= 16).  Returns BPIDA_OK or BPIDA_EINVAL.

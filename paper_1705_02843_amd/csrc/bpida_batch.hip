@@ -540,21 +540,26 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
       return false;
     }
     if (avail + kGrow > CAP) {
-      // LDS would overflow: move the 64 oldest entries to the queue
-      const uint32_t p = (bot + (uint32_t)lane) & (CAP - 1);
-      const S t = st[p];
-      const uint16_t m = sm[p];
-      WAVE_SYNC();
-      if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
-      if (q_push(A, (uint64_t)t, wide ? (uint64_t)((unsigned __int128)t >> 64) : 0ull, m, 64, inst,
-                 wide)) {
-        wc.pushes += 1;
-      } else if (lane == 0) {
-        __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
-        atomicOr(&q->err, 2);  // entries dropped: the call reports BPIDA_ENOMEM
-      }
-      bot += 64;
-      avail -= 64;
+      // LDS could overflow: move the oldest entries to the queue, 64 at a
+      // time, until the largest round fits.  One chunk is not always enough:
+      // a 64-node round can add up to 128 entries (three children a node),
+      // more than one chunk takes away.
+      do {
+        const uint32_t p = (bot + (uint32_t)lane) & (CAP - 1);
+        const S t = st[p];
+        const uint16_t m = sm[p];
+        WAVE_SYNC();
+        if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
+        if (q_push(A, (uint64_t)t, wide ? (uint64_t)((unsigned __int128)t >> 64) : 0ull, m, 64,
+                   inst, wide)) {
+          wc.pushes += 1;
+        } else if (lane == 0) {
+          __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
+          atomicOr(&q->err, 2);  // entries dropped: the call reports BPIDA_ENOMEM
+        }
+        bot += 64;
+        avail -= 64;
+      } while (avail + kGrow > CAP);
     } else if (avail >= dmin && (tick & A.donate_mask) == 0) {
       // donation when workgroups wait on tickets no queued chunk covers: the
       // oldest min(window, avail) entries (the shallowest, largest subtrees)
@@ -593,6 +598,9 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
     } else {
       top = bp_round64w<W, CAP>(st, sm, top, kp, goals, smax);
     }
+    // the spill above keeps every round inside the ring; a round that ended
+    // past it would have overwritten entries (reported, never silent)
+    if (top - bot > (uint32_t)CAP && lane == 0) atomicOr(&q->err, 32);
     expanded += (uint64_t)kp;
     wc.rounds += 1;
     if (A.first_solution) {
@@ -794,6 +802,7 @@ __global__ void batch_status_kernel(const InstState* __restrict__ is, int n,
   int32_t v = done;
   if (*split_err) v = -6;                    // BPIDA_EINTERNAL
   else if (q->err & (1 | 2 | 16)) v = -4;   // BPIDA_ENOMEM
+  else if (q->err & 32) v = -6;             // LDS ring overrun: BPIDA_EINTERNAL
   else if (done == 0) v = -6;               // stopped by the watchdog or the deadline
   st[k] = v;
 }

@@ -182,3 +182,31 @@ def test_mixed_batch_with_bad_states(B):
         want = oracle_of([items[k] for k in ks], w)
         for j, k in enumerate(ks):
             assert ln[k] == want.length[j] and (nodes[k] == want.nodes[j]).all(), (w, k)
+
+
+@pytest.mark.parametrize("depth", [0, 6])
+def test_5x5_high_slack_smallest_ring_exact(B, depth):
+    """5x5 instances whose final limit leaves a slack of 18-20 at the start
+    state, on the smallest ring a 5x5 allows (256 wide entries).  High slack
+    keeps nearly every legal move, so 64-node rounds grow the stack by more
+    than one spilled chunk per round for long stretches: the spill must
+    continue until the next round fits, and the run must stay exact with no
+    error bit set."""
+    g = _golden("c4_mixed_w5")
+    assert g is not None
+    pick = [r for r in g["instances"]
+            if r["length"] - r["limits"][0] >= 18 and sum(r["nodes"]) < 3e7]
+    assert len(pick) >= 8
+    states = np.array([list(bytes.fromhex(r["state"])) for r in pick], np.uint8)
+    assert states.shape == (len(pick), 25)
+    B.set_option("lds_stack_capacity", 512)
+    B.set_option("nodes_per_round", 64)
+    B.set_option("frontier_depth", depth)
+    print("case: 5x5 high slack, ring 512, D=%d, %d states" % (depth, len(pick)), flush=True)
+    rc, ln, nodes = B.solve_raw(states, 5)
+    assert rc == B.OK, B.strerror(rc)
+    assert B.last_stats()["error_bits"] == 0
+    for i, r in enumerate(pick):
+        m = len(r["nodes"])
+        assert ln[i] == r["length"], i
+        assert list(nodes[i, :m]) == r["nodes"] and not nodes[i, m:].any(), i
