@@ -505,6 +505,24 @@ struct WgCounters {
   uint64_t rounds = 0, pushes = 0, voluntary = 0;
 };
 
+// Moves LDS stack entries [src, src + n) down to [dst, dst + n), dst < src,
+// 64 at a time in ascending order: every entry is read before anything is
+// written over it.
+template <typename S>
+__device__ __forceinline__ void move_down(S* st, uint16_t* sm, uint32_t dst, uint32_t src, uint32_t n) {
+  const uint32_t lane = threadIdx.x;
+  for (uint32_t i = 0; i < n; i += 64u) {
+    const uint32_t k = i + lane;
+    if (k < n) {
+      const S t = st[src + k];
+      const uint16_t m = sm[src + k];
+      st[dst + k] = t;
+      sm[dst + k] = m;
+    }
+  }
+  WAVE_SYNC();
+}
+
 // Searches one unit (the chunk already in LDS entries [0, cnt)) of an
 // instance of width W until its stack is empty: BPDFS rounds, with spills
 // to the queue when LDS would overflow and donations to waiting workgroups.
@@ -529,11 +547,13 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   // subtrees on one workgroup.  Default: four rounds' worth of pops, at most
   // half the ring.
   const int dmin = A.donate_min > 0 ? A.donate_min : min(4 * NPL, CAP / 2);
-  int smax = INT_MIN;
-  uint32_t top = (uint32_t)cnt, bot = 0;  // unsigned: they wrap, top - bot stays small
-  if (A.first_solution && wave_bcast(lane == 0 ? ld_relaxed(&A.is[inst].stop) : 0)) top = bot;
-  while (top != bot) {
-    int avail = (int)(top - bot);
+  // The LDS stack holds entries [0, top), the oldest at 0.  Entries taken
+  // from the bottom (spills, donations) make the rest move down, so a
+  // position never wraps and a round addresses the stack without a mask.
+  uint32_t top = (uint32_t)cnt;
+  if (A.first_solution && wave_bcast(lane == 0 ? ld_relaxed(&A.is[inst].stop) : 0)) top = 0;
+  while (top != 0) {
+    int avail = (int)top;
     ++tick;
     if ((tick & 1023u) == 0 && wall_clock64() > deadline) {
       if (lane == 0) atomicOr(&q->err, 8);
@@ -545,9 +565,8 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
       // a 64-node round can add up to 128 entries (three children a node),
       // more than one chunk takes away.
       do {
-        const uint32_t p = (bot + (uint32_t)lane) & (CAP - 1);
-        const S t = st[p];
-        const uint16_t m = sm[p];
+        const S t = st[lane];
+        const uint16_t m = sm[lane];
         WAVE_SYNC();
         if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
         if (q_push(A, (uint64_t)t, wide ? (uint64_t)((unsigned __int128)t >> 64) : 0ull, m, 64,
@@ -557,7 +576,8 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
           __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
           atomicOr(&q->err, 2);  // entries dropped: the call reports BPIDA_ENOMEM
         }
-        bot += 64;
+        move_down(st, sm, 0u, 64u, top - 64u);
+        top -= 64u;
         avail -= 64;
       } while (avail + kGrow > CAP);
     } else if (avail >= dmin && (tick & A.donate_mask) == 0) {
@@ -569,23 +589,23 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
       if (wave_bcast(want)) {
         const int w = min(avail, A.donate_window) & ~1;
         const int h = w >> 1;
-        const uint32_t pg = (bot + 2u * (uint32_t)lane) & (CAP - 1);
-        const uint32_t pk = (bot + 2u * (uint32_t)lane + 1u) & (CAP - 1);
-        const S tg = st[pg], tk = st[pk];
-        const uint16_t mg = sm[pg], mk = sm[pk];
+        // (positions up to 127: inside the stack's storage, read for every lane)
+        const S tg = st[2 * lane], tk = st[2 * lane + 1];
+        const uint16_t mg = sm[2 * lane], mk = sm[2 * lane + 1];
         WAVE_SYNC();
         if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
         if (q_push(A, (uint64_t)tg, wide ? (uint64_t)((unsigned __int128)tg >> 64) : 0ull, mg, h,
                    inst, wide)) {
           wc.pushes += 1;
           wc.voluntary += 1;
+          // the kept half becomes the bottom, the entries above the window
+          // close up behind it
           if (lane < h) {
-            const uint32_t pn = (bot + (uint32_t)(h + lane)) & (CAP - 1);
-            st[pn] = tk;
-            sm[pn] = mk;
+            st[lane] = tk;
+            sm[lane] = mk;
           }
-          WAVE_SYNC();
-          bot += (uint32_t)h;
+          move_down(st, sm, (uint32_t)h, (uint32_t)w, top - (uint32_t)w);
+          top -= (uint32_t)h;
           avail -= h;
         } else if (lane == 0) {
           __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
@@ -596,11 +616,11 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
     if constexpr (NPL == 16) {
       top = bp_round<CAP>((uint64_t*)st, sm, top, kp, limit, M, goals, fmin);
     } else {
-      top = bp_round64w<W, CAP>(st, sm, top, kp, goals, smax);
+      top = bp_round64w<W, CAP>(st, sm, top, kp, goals);
     }
     // the spill above keeps every round inside the ring; a round that ended
     // past it would have overwritten entries (reported, never silent)
-    if (top - bot > (uint32_t)CAP && lane == 0) atomicOr(&q->err, 32);
+    if (top > (uint32_t)CAP && lane == 0) atomicOr(&q->err, 32);
     expanded += (uint64_t)kp;
     wc.rounds += 1;
     if (A.first_solution) {
@@ -614,10 +634,11 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
       if ((tick & 63u) == 0 && wave_bcast(lane == 0 ? ld_relaxed(&A.is[inst].stop) : 0)) break;
     }
   }
-  if (NPL == 64) {
-    const int sm_w = wave_max(smax);
-    fmin = sm_w == INT_MIN ? INT_MAX : limit - sm_w;
-  }
+  // 64-node rounds: a pruned child always has f = limit + 2 (bp_round64w),
+  // and every limit below the optimum prunes one: below the optimum, a path
+  // of approaching moves from a slack-0 node cannot reach the goal, so it
+  // ends at a node whose remaining moves all go away and are pruned
+  if (NPL == 64) fmin = limit + 2;
   return true;
 }
 

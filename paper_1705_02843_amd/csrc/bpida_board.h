@@ -164,11 +164,26 @@ __device__ __forceinline__ uint32_t mul_u24(uint32_t k, uint32_t t) {
   return r;
 }
 
+// 24-bit signed product (k = -K for a constant K below 2^24, t a tile).
+__device__ __forceinline__ uint32_t mul_i24(int k, uint32_t t) {
+  uint32_t r;
+  asm("v_mul_i32_i24 %0, %1, %2" : "=v"(r) : "v"(k), "v"(t));
+  return r;
+}
+
 // a * b + c on 24-bit signed a, b (one instruction; the compiler would
 // otherwise shift and subtract).
 __device__ __forceinline__ uint32_t mad_i24(uint32_t a, int b, uint32_t c) {
   uint32_t r;
   asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
+
+// v where the lane's bit of the wave mask lm is set, else 0: the mask is read
+// from scalar registers, with no per-lane compare.
+__device__ __forceinline__ uint32_t sel_lanes(uint64_t lm, uint32_t v) {
+  uint32_t r;
+  asm("v_cndmask_b32 %0, 0, %1, %2" : "=v"(r) : "v"(v), "s"(lm));
   return r;
 }
 
@@ -193,8 +208,7 @@ struct NodeCtx {
 // One move for every lane of a 64-node round (see bp_round64w).
 template <int W, int CAP, int A>
 __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm, uint32_t& out,
-                                          const typename Board<W>::S s, const NodeCtx& c,
-                                          uint32_t& upm) {
+                                          const typename Board<W>::S s, const NodeCtx& c) {
   using B = Board<W>;
   using S = typename B::S;
   constexpr int delta = A == 0 ? -W : A == 1 ? -1 : A == 2 ? 1 : W;
@@ -206,24 +220,32 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
   const uint32_t sh_n = shu & (8u * sizeof(S) - 1u);
   const uint32_t x = (uint32_t)(s >> sh_n);  // tile t in the low BITS bits
   const uint32_t up = B::template up<A>(x, c.rowi, c.coli);
-  upm |= up << A;
   const uint32_t kb = opaque((c.lmx >> (A + 4 * up)) & 1u);
   const uint64_t km = __builtin_amdgcn_uicmp(kb, 0u, 33);  // lanes with kb != 0
   if (kb != 0u) {
     // successor: t moves from n to b, i.e. the packed word changes by
     // t * (base^b - base^n) = +/- (K * t) << (BITS * min(b, n))
-    uint32_t kt;
-    if constexpr (K < (1u << 24)) kt = mul_u24(K, x & B::MASK);
-    else kt = K * (x & B::MASK);  // 5x5 rows: K = 2^25 - 1
-    const S d = (S)kt << (A < 2 ? shu : c.shb);
-    const S cs = A < 2 ? s + d : s - d;
+    S cs;
+    if constexpr (A >= 2 && sizeof(S) == 8) {
+      // the subtraction as the addition of -K t sign-extended to 64 bits:
+      // one 64-bit add instead of a subtract with borrow
+      const uint32_t nkt = mul_i24(-(int)K, x & B::MASK);
+      cs = s + (((0xFFFFFFFFull << 32) | nkt) << c.shb);
+    } else {
+      uint32_t kt;
+      if constexpr (K < (1u << 24)) kt = mul_u24(K, x & B::MASK);
+      else kt = K * (x & B::MASK);  // 5x5 rows: K = 2^25 - 1
+      const S d = (S)kt << (A < 2 ? shu : c.shb);
+      cs = A < 2 ? s + d : s - d;
+    }
     // stack meta: n | (3 - A) << 5 | (slack - 2 up) << 8
     const uint32_t cm = mad_i24(up, -512, c.mbase) + (uint32_t)(delta + ((3 - A) << 5));
     const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
-    // byte offsets into the ring: entry (out + r) mod CAP
+    // byte offsets into the stack: entry out + r (below CAP: the caller
+    // leaves room for the largest round)
     constexpr uint32_t LS = sizeof(S) == 8 ? 3 : 4;
-    const uint32_t pst = ((r + out) << LS) & ((uint32_t)(CAP << LS) - 1u);
+    const uint32_t pst = (r + out) << LS;
     *(S*)((char*)st + pst) = cs;
     *(uint16_t*)((char*)sm + (pst >> (LS - 1))) = (uint16_t)cm;
   }
@@ -231,22 +253,24 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
 }
 
 // One BPDFS round with one popped node per lane, for any board width: pops
-// kp = min(64, top - bot) nodes, tests them for the goal and pushes every
-// legal, non-undoing child with f <= limit.  The caller guarantees
-// top - bot + 3*kp <= CAP.  Ring positions are unsigned and wrap.  `smax` tracks the largest slack of a pruned
-// child (always slack - 2 of a node whose tile moves away from its goal).
+// kp = min(64, top) nodes from a stack of entries [0, top), tests them for
+// the goal and pushes every legal, non-undoing child with f <= limit.  The
+// caller guarantees top + 3*kp <= CAP (no position wraps).  The
+// round does not track the f of pruned children: every slack on the stack is
+// even (f keeps the parity of h0, and so does the limit), so a child is
+// pruned only from slack 0, moving a tile away from its goal, and its f is
+// the limit + 2.
 template <int W, int CAP>
 __device__ __forceinline__ uint32_t bp_round64w(typename Board<W>::S* st, uint16_t* sm, uint32_t top, int kp,
-                                           int& goals, int& smax) {
+                                           int& goals) {
   using B = Board<W>;
   using S = typename B::S;
   const int lane = threadIdx.x;
   const uint32_t base = top - (uint32_t)kp;
   constexpr uint32_t LS = sizeof(S) == 8 ? 3 : 4;
-  const uint32_t pst = ((base + (uint32_t)lane) << LS) & ((uint32_t)(CAP << LS) - 1u);
+  const uint32_t pst = (base + (uint32_t)lane) << LS;
   const S s = *(const S*)((const char*)st + pst);
   const uint32_t m = *(const uint16_t*)((const char*)sm + (pst >> (LS - 1)));
-  const bool act = lane < kp;
   const uint64_t actm = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
   uint64_t gm;
   if constexpr (sizeof(S) == 8) gm = __builtin_amdgcn_uicmpl((uint64_t)s, (uint64_t)B::goal(), 32);
@@ -262,22 +286,19 @@ __device__ __forceinline__ uint32_t bp_round64w(typename Board<W>::S* st, uint16
   } else {
     lm = B::legal(c.b) & ~(1u << fb);
   }
-  lm = act ? lm : 0u;
   // moves that survive: any legal one if its tile approaches its goal, and
-  // only with slack >= 2 if it moves away
+  // only with slack >= 2 if it moves away (bits 0..3 and 4..7 of lm * 17);
+  // lanes past kp keep nothing
   const bool roomy = m >= (2u << 8);
-  c.lmx = ((roomy ? lm : 0u) << 4) | lm;
+  c.lmx = mul_u24(lm, sel_lanes(actm, roomy ? 17u : 1u));
   c.rowi = B::row_part(c.b);
   c.coli = B::col_part(c.b);
   c.mbase = (m & 0xFF00u) | c.b;
-  uint32_t upm = 0;
   uint32_t out = base;
-  bp_move_w<W, CAP, 0>(st, sm, out, s, c, upm);
-  bp_move_w<W, CAP, 1>(st, sm, out, s, c, upm);
-  bp_move_w<W, CAP, 2>(st, sm, out, s, c, upm);
-  bp_move_w<W, CAP, 3>(st, sm, out, s, c, upm);
-  // a pruned child exists iff a legal move goes away from the goal at slack < 2
-  if (!roomy && (upm & lm) != 0u) smax = max(smax, (int)(m >> 8) - 2);
+  bp_move_w<W, CAP, 0>(st, sm, out, s, c);
+  bp_move_w<W, CAP, 1>(st, sm, out, s, c);
+  bp_move_w<W, CAP, 2>(st, sm, out, s, c);
+  bp_move_w<W, CAP, 3>(st, sm, out, s, c);
   WAVE_SYNC();
   return out;
 }
