@@ -89,7 +89,8 @@ int bpida_solve(const uint8_t *states, int32_t n_instances, int32_t width, int32
  * (one persistent launch for all of them).  widths: host, n int32 in 3..5.
  * states: host, the instances' bytes back to back (instance i takes
  * widths[i]^2 bytes).  Outputs as in bpida_solve.  5x5 instances need an LDS
- * ring of at least 512 entries (the default), 3x3 of 256.
+ * stack of at least 1024 entries (the default), 3x3 of 256, 4x4 of 512 with
+ * 64-node rounds; a smaller one is BPIDA_EINVAL.
  */
 int bpida_solve_mixed(const uint8_t *states, const int32_t *widths, int32_t n_instances,
                       int32_t *out_len, uint64_t *out_nodes_per_threshold);
@@ -190,9 +191,12 @@ int bpida_server_stop(void);
  *   "lds_stack_capacity" DFS stack entries per workgroup in LDS: 128, 256,
  *                        512, 1024 or 2048, or -1 (default): 512 for 16-node
  *                        rounds, 1024 for 64-node rounds (64-node rounds need
- *                        at least 512; smaller is BPIDA_EINVAL at solve time);
- *                        deeper entries spill to HBM (plain) or to the work
- *                        queue (batched)
+ *                        at least 512 on 4x4 and 1024 on 5x5, 256 on 3x3;
+ *                        smaller is BPIDA_EINVAL at solve time); deeper
+ *                        entries spill to HBM (plain) or to the work queue
+ *                        (batched).  A smaller stack spills more: with 512
+ *                        entries, batches of thousands of 4x4 instances can
+ *                        overflow the default work queue (BPIDA_ENOMEM)
  *   "nodes_per_round"    batched mode: 64 (default) pops one node per lane and
  *                        each lane tries the four moves; 16 uses Alg. 1's map
  *                        (lane l expands node l/4 with move l%4).  Plain mode

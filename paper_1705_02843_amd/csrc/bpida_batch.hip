@@ -555,9 +555,14 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   while (top != 0) {
     int avail = (int)top;
     ++tick;
-    if ((tick & 1023u) == 0 && wall_clock64() > deadline) {
-      if (lane == 0) atomicOr(&q->err, 8);
-      return false;
+    if ((tick & 1023u) == 0) {
+      if (wall_clock64() > deadline) {
+        if (lane == 0) atomicOr(&q->err, 8);
+        return false;
+      }
+      // work was dropped somewhere (every count is void and the call
+      // reports BPIDA_ENOMEM): stop instead of searching on
+      if (!A.server && (ld_relaxed(&q->err) & kErrFatal)) return false;
     }
     if (avail + kGrow > CAP) {
       // LDS could overflow: move the oldest entries to the queue, 64 at a
@@ -674,6 +679,7 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
     if (lane == 0) i = __hip_atomic_fetch_add(&q->seed_next, 1, __ATOMIC_RELAXED, AGENT);
     i = wave_bcast(i);
     if (i >= A.n) break;
+    if (ld_relaxed(&q->err) & kErrFatal) break;  // work already lost: stop seeding
     if (A.is[i].done != 0) continue;
     if (seed_limit(A, i, st, sm)) complete_limit(A, i, st, sm);
   }
@@ -695,6 +701,7 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
     int cnt, inst;
     if (!q_take(A, ticket, t, th, m, cnt, inst)) {
       if (ld_relaxed(&q->remaining) <= 0) break;
+      if (!A.server && (ld_relaxed(&q->err) & kErrFatal)) break;
       const uint64_t now = wall_clock64();
       // queue activity seen by this idle workgroup (lane 0's view)
       uint64_t act = 0;
@@ -822,7 +829,7 @@ __global__ void batch_status_kernel(const InstState* __restrict__ is, int n,
   const int32_t done = is[k].done;
   int32_t v = done;
   if (*split_err) v = -6;                    // BPIDA_EINTERNAL
-  else if (q->err & (1 | 2 | 16)) v = -4;   // BPIDA_ENOMEM
+  else if (q->err & kErrFatal) v = -4;      // BPIDA_ENOMEM
   else if (q->err & 32) v = -6;             // LDS ring overrun: BPIDA_EINTERNAL
   else if (done == 0) v = -6;               // stopped by the watchdog or the deadline
   st[k] = v;

@@ -381,14 +381,17 @@ void tree_size(const Workspace& W, int w, int D, int64_t* stride, int64_t* max_r
   }
 }
 
-// Ring capacity a width needs with this ring option (64-node rounds need
-// 256 entries; 5x5 entries take two slots of the LDS budget).
-// 3x3 and 5x5 instances always run 64-node rounds; a 5x5 state takes two
-// ring entries, so its ring holds cap / 2 of them.
-bool ring_fits(int w, int cap) {
-  if (w == 4) return true;
+// Whether a width can run with this LDS stack option.  3x3 and 5x5
+// instances always run 64-node rounds; a 5x5 state takes two entries, so its
+// stack holds cap / 2 of them.  A 64-node round can add 192 entries, so a
+// stack of 256 spills on almost every round: the spilled chunks, taken
+// oldest first, turn the search breadth-first and the work queue grows
+// without bound on 4x4 and 5x5 trees (measured: 2 million chunks were not
+// enough).  3x3 trees are small enough for 256.
+bool ring_fits(int w, int cap, int npl) {
   if (w == 3) return cap >= 256;
-  return cap / 2 >= 256;
+  if (w == 4) return npl == 16 || cap >= 512;
+  return cap / 2 >= 512;
 }
 
 int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
@@ -421,7 +424,7 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
   if (!h_widths) {
     int64_t mr = 0;
     tree_size(W, width, D, &stride, &mr);
-    if (!ring_fits(width, cap)) return BPIDA_EINVAL;
+    if (!ring_fits(width, cap, npl)) return BPIDA_EINVAL;
     tree_nodes = stride * n;
     seed_chunks = (int64_t)n * ((mr + kQChunk - 1) / kQChunk);
   } else {
@@ -429,7 +432,7 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
     int64_t bytes = 0;
     for (int i = 0; i < n; ++i) {
       const int w = h_widths[i];
-      if (w < 3 || w > 5 || !ring_fits(w, cap)) return BPIDA_EINVAL;
+      if (w < 3 || w > 5 || !ring_fits(w, cap, npl)) return BPIDA_EINVAL;
       any5 = any5 || w == 5;
       int64_t sw = 0, mr = 0;
       tree_size(W, w, D, &sw, &mr);
@@ -745,7 +748,7 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     const int npl = (int)O.nodes_per_round;
     const int cap = cap_for(O, npl);
     const int per_cu = batch4_max_blocks_per_cu(cap, npl);
-    if (per_cu <= 0) return BPIDA_EINVAL;
+    if (per_cu <= 0 || !ring_fits(4, cap, npl)) return BPIDA_EINVAL;
     int64_t grid = (int64_t)per_cu * W.num_cu;
     if (O.max_workgroups > 0) grid = std::min<int64_t>(grid, O.max_workgroups);
     if (grid < 2) return BPIDA_EINVAL;  // one admitter plus at least one searcher
@@ -905,7 +908,7 @@ extern "C" int bpida_server_stop(void) {
     stats[12] = (uint64_t)V.grid;
     stats[13] = (uint64_t)(uint32_t)qc.err;
     memcpy(g_stats, stats, sizeof stats);
-    if (qc.err & (1 | 2 | 16)) return BPIDA_ENOMEM;
+    if (qc.err & kErrFatal) return BPIDA_ENOMEM;
     if (qc.err) return BPIDA_EINTERNAL;
     return BPIDA_OK;
   } catch (...) {

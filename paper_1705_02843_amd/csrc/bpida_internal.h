@@ -133,6 +133,11 @@ constexpr int kWalkStride = kWalkCells * (kMaxDepth + 1);
 constexpr int kQChunk = 64;  // stack entries per queue chunk
 
 // One queue slot: up to 64 stack entries of one instance at its current limit.
+// Queue error bits after which work is lost (1 queue full while seeding,
+// 2 entries dropped, 16 a ticket lost): the batched call reports
+// BPIDA_ENOMEM and its workgroups stop early.
+constexpr int32_t kErrFatal = 1 | 2 | 16;
+
 struct alignas(128) QChunk {
   uint64_t tiles[kQChunk];  // packed states, bits 0..63
   uint64_t hi[kQChunk];     // bits 64..127 (5x5 only)

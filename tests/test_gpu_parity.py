@@ -274,13 +274,36 @@ def test_batched_uneven_batch_exact(opts):
     _say("stats: %s" % st)
 
 
-def test_batched_rejects_ring_too_small_for_64_node_rounds(opts):
+@pytest.mark.parametrize("cap", [128, 256])
+def test_batched_rejects_ring_too_small_for_64_node_rounds(opts, cap):
+    """4x4 with 64-node rounds needs 512 entries: a round can add 192, so a
+    smaller stack spills on almost every round and the queue runs away."""
     B = opts
     set_mode(B, "batched")
-    B.set_option("lds_stack_capacity", 128)  # 64-node rounds need 256 entries
+    B.set_option("lds_stack_capacity", cap)
     states, _, _ = load_golden("c1_walk40")
     rc, _, _ = B.solve_raw(states[:2])
     assert rc == B.EINVAL
+
+
+def test_lost_work_fails_fast(opts):
+    """A queue too small for the batch drops work: the call reports
+    BPIDA_ENOMEM, and the workgroups stop instead of searching on (or
+    waiting for the idle watchdog).  One workgroup seeds all 100 instances
+    before it takes anything, so a 64-chunk queue overflows for sure."""
+    import time
+    B = opts
+    set_mode(B, "batched")
+    B.set_option("queue_capacity", 64)
+    B.set_option("max_workgroups", 1)
+    states, _, _ = load_golden("c2_md30_38")
+    _say("case: c2 with a 64-chunk work queue, one workgroup")
+    t = time.time()
+    rc, _, _ = B.solve_raw(states)
+    dt = time.time() - t
+    assert rc == B.ENOMEM, B.strerror(rc)
+    assert B.last_stats()["error_bits"] & (1 | 2 | 16)
+    assert dt < 5.0, dt
 
 
 def test_c3_4096_batched_exact_where_stored_and_valid_everywhere(opts):
