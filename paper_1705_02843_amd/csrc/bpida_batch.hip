@@ -552,10 +552,15 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   // position never wraps and a round addresses the stack without a mask.
   uint32_t top = (uint32_t)cnt;
   if (A.first_solution && wave_bcast(lane == 0 ? ld_relaxed(&A.is[inst].stop) : 0)) top = 0;
+  // The deadline, donation and first-solution polls come every
+  // min(64, donate_every) rounds, a period that divides each of theirs; the
+  // rounds in between test only whether the next round needs a spill.
+  const uint32_t poll_mask = min(A.donate_mask, 63u);
   while (top != 0) {
     int avail = (int)top;
     ++tick;
-    if ((tick & 1023u) == 0) {
+    const bool poll = (tick & poll_mask) == 0;
+    if (poll && (tick & 1023u) == 0) {
       if (wall_clock64() > deadline) {
         if (lane == 0) atomicOr(&q->err, 8);
         return false;
@@ -585,7 +590,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
         top -= 64u;
         avail -= 64;
       } while (avail + kGrow > CAP);
-    } else if (avail >= dmin && (tick & A.donate_mask) == 0) {
+    } else if (poll && avail >= dmin && (tick & A.donate_mask) == 0) {
       // donation when workgroups wait on tickets no queued chunk covers: the
       // oldest min(window, avail) entries (the shallowest, largest subtrees)
       // are split alternately, so donor and receiver each keep about half
@@ -625,7 +630,9 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
     }
     // the spill above keeps every round inside the ring; a round that ended
     // past it would have overwritten entries (reported, never silent)
-    if (top > (uint32_t)CAP && lane == 0) atomicOr(&q->err, 32);
+    if (top > (uint32_t)CAP) {
+      if (lane == 0) atomicOr(&q->err, 32);
+    }
     expanded += (uint64_t)kp;
     wc.rounds += 1;
     if (A.first_solution) {
@@ -636,7 +643,8 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
         if (lane == 0) __hip_atomic_store(&A.is[inst].stop, 1, __ATOMIC_RELAXED, AGENT);
         break;
       }
-      if ((tick & 63u) == 0 && wave_bcast(lane == 0 ? ld_relaxed(&A.is[inst].stop) : 0)) break;
+      if (poll && (tick & 63u) == 0 && wave_bcast(lane == 0 ? ld_relaxed(&A.is[inst].stop) : 0))
+        break;
     }
   }
   // 64-node rounds: a pruned child always has f = limit + 2 (bp_round64w),

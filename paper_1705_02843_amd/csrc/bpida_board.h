@@ -182,8 +182,12 @@ __device__ __forceinline__ uint32_t mad_i24(uint32_t a, int b, uint32_t c) {
 // v where the lane's bit of the wave mask lm is set, else 0: the mask is read
 // from scalar registers, with no per-lane compare.
 __device__ __forceinline__ uint32_t sel_lanes(uint64_t lm, uint32_t v) {
+  // the mask is wave-uniform; readfirstlane tells the compiler so (and
+  // folds away when it already knows)
+  const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(lm >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)lm);
   uint32_t r;
-  asm("v_cndmask_b32 %0, 0, %1, %2" : "=v"(r) : "v"(v), "s"(lm));
+  asm("v_cndmask_b32 %0, 0, %1, %2" : "=v"(r) : "v"(v), "s"(m));
   return r;
 }
 
