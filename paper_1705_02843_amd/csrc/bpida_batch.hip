@@ -560,14 +560,49 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
     int avail = (int)top;
     ++tick;
     const bool poll = (tick & poll_mask) == 0;
-    if (poll && (tick & 1023u) == 0) {
-      if (wall_clock64() > deadline) {
-        if (lane == 0) atomicOr(&q->err, 8);
-        return false;
+    if (poll) {
+      if ((tick & 1023u) == 0) {
+        if (wall_clock64() > deadline) {
+          if (lane == 0) atomicOr(&q->err, 8);
+          return false;
+        }
+        // work was dropped somewhere (every count is void and the call
+        // reports BPIDA_ENOMEM): stop instead of searching on
+        if (!A.server && (ld_relaxed(&q->err) & kErrFatal)) return false;
       }
-      // work was dropped somewhere (every count is void and the call
-      // reports BPIDA_ENOMEM): stop instead of searching on
-      if (!A.server && (ld_relaxed(&q->err) & kErrFatal)) return false;
+      if (avail + kGrow <= CAP && avail >= dmin && (tick & A.donate_mask) == 0) {
+        // donation when workgroups wait on tickets no queued chunk covers:
+        // the oldest min(window, avail) entries (the shallowest, largest
+        // subtrees) are split alternately, so donor and receiver each keep
+        // about half
+        int want = 0;
+        if (lane == 0) want = (int64_t)(ld_relaxed(&q->head) - ld_relaxed(&q->tail)) > 0;
+        if (wave_bcast(want)) {
+          const int w = min(avail, A.donate_window) & ~1;
+          const int h = w >> 1;
+          // (positions up to 127: inside the stack's storage, read for every lane)
+          const S tg = st[2 * lane], tk = st[2 * lane + 1];
+          const uint16_t mg = sm[2 * lane], mk = sm[2 * lane + 1];
+          WAVE_SYNC();
+          if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
+          if (q_push(A, (uint64_t)tg, wide ? (uint64_t)((unsigned __int128)tg >> 64) : 0ull, mg, h,
+                     inst, wide)) {
+            wc.pushes += 1;
+            wc.voluntary += 1;
+            // the kept half becomes the bottom, the entries above the window
+            // close up behind it
+            if (lane < h) {
+              st[lane] = tk;
+              sm[lane] = mk;
+            }
+            move_down(st, sm, (uint32_t)h, (uint32_t)w, top - (uint32_t)w);
+            top -= (uint32_t)h;
+            avail -= h;
+          } else if (lane == 0) {
+            __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
+          }
+        }
+      }
     }
     if (avail + kGrow > CAP) {
       // LDS could overflow: move the oldest entries to the queue, 64 at a
@@ -590,37 +625,6 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
         top -= 64u;
         avail -= 64;
       } while (avail + kGrow > CAP);
-    } else if (poll && avail >= dmin && (tick & A.donate_mask) == 0) {
-      // donation when workgroups wait on tickets no queued chunk covers: the
-      // oldest min(window, avail) entries (the shallowest, largest subtrees)
-      // are split alternately, so donor and receiver each keep about half
-      int want = 0;
-      if (lane == 0) want = (int64_t)(ld_relaxed(&q->head) - ld_relaxed(&q->tail)) > 0;
-      if (wave_bcast(want)) {
-        const int w = min(avail, A.donate_window) & ~1;
-        const int h = w >> 1;
-        // (positions up to 127: inside the stack's storage, read for every lane)
-        const S tg = st[2 * lane], tk = st[2 * lane + 1];
-        const uint16_t mg = sm[2 * lane], mk = sm[2 * lane + 1];
-        WAVE_SYNC();
-        if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
-        if (q_push(A, (uint64_t)tg, wide ? (uint64_t)((unsigned __int128)tg >> 64) : 0ull, mg, h,
-                   inst, wide)) {
-          wc.pushes += 1;
-          wc.voluntary += 1;
-          // the kept half becomes the bottom, the entries above the window
-          // close up behind it
-          if (lane < h) {
-            st[lane] = tk;
-            sm[lane] = mk;
-          }
-          move_down(st, sm, (uint32_t)h, (uint32_t)w, top - (uint32_t)w);
-          top -= (uint32_t)h;
-          avail -= h;
-        } else if (lane == 0) {
-          __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
-        }
-      }
     }
     const int kp = min(avail, NPL);
     if constexpr (NPL == 16) {
