@@ -31,6 +31,12 @@ __device__ __forceinline__ uint64_t ld_relaxed(uint64_t* p) {
 __device__ __forceinline__ int32_t ld_relaxed(int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, AGENT);
 }
+// The value lane 0 loads, in every lane: a branch on it is uniform (a
+// per-lane load, even of one address, makes the compiler treat the branch
+// as divergent).
+__device__ __forceinline__ int32_t ld_wave(int32_t* p) {
+  return __builtin_amdgcn_readfirstlane(ld_relaxed(p));
+}
 
 // ---------------------------------------------------------------------------
 // Ticket queue of chunks.  Producers and consumers take tickets with a
@@ -529,7 +535,7 @@ __device__ __forceinline__ void move_down(S* st, uint16_t* sm, uint32_t dst, uin
 // NPL = nodes popped per round: 16 (lane l expands node l/4 with move l%4,
 // Alg. 1's thread -> action map; width 4 only) or 64 (one node per lane,
 // four moves each).  Returns false if the time budget ran out (abandoned).
-template <int W, int CAP, int NPL>
+template <int W, int CAP, int NPL, bool FS>
 __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board<W>::S* st,
                          uint16_t* sm, int cnt, WgCounters& wc, uint32_t& tick, uint64_t deadline,
                          uint64_t& expanded, int& goals, int& fmin) {
@@ -551,7 +557,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   // from the bottom (spills, donations) make the rest move down, so a
   // position never wraps and a round addresses the stack without a mask.
   uint32_t top = (uint32_t)cnt;
-  if (A.first_solution && wave_bcast(lane == 0 ? ld_relaxed(&A.is[inst].stop) : 0)) top = 0;
+  if (FS && wave_bcast(lane == 0 ? ld_relaxed(&A.is[inst].stop) : 0)) top = 0;
   // The deadline, donation and first-solution polls come every
   // min(64, donate_every) rounds, a period that divides each of theirs; the
   // rounds in between test only whether the next round needs a spill.
@@ -562,13 +568,14 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
     const bool poll = (tick & poll_mask) == 0;
     if (poll) {
       if ((tick & 1023u) == 0) {
-        if (wall_clock64() > deadline) {
-          if (lane == 0) atomicOr(&q->err, 8);
+        // the time budget is spent, or work was dropped somewhere (every
+        // count is void and the call reports BPIDA_ENOMEM): stop instead of
+        // searching on
+        const bool late = wall_clock64() > deadline;
+        if (late || (!A.server && (ld_wave(&q->err) & kErrFatal))) {
+          if (late && lane == 0) atomicOr(&q->err, 8);
           return false;
         }
-        // work was dropped somewhere (every count is void and the call
-        // reports BPIDA_ENOMEM): stop instead of searching on
-        if (!A.server && (ld_relaxed(&q->err) & kErrFatal)) return false;
       }
       if (avail + kGrow <= CAP && avail >= dmin && (tick & A.donate_mask) == 0) {
         // donation when workgroups wait on tickets no queued chunk covers:
@@ -634,12 +641,10 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
     }
     // the spill above keeps every round inside the ring; a round that ended
     // past it would have overwritten entries (reported, never silent)
-    if (top > (uint32_t)CAP) {
-      if (lane == 0) atomicOr(&q->err, 32);
-    }
+    if (top > (uint32_t)CAP) atomicOr(&q->err, 32);  // every lane: a uniform branch
     expanded += (uint64_t)kp;
     wc.rounds += 1;
-    if (A.first_solution) {
+    if constexpr (FS) {
       // first-solution mode (Alg. 1 returns at its first goal): the unit that
       // expands a goal stops its instance; the others see the flag within 64
       // rounds and drop their stacks
@@ -691,7 +696,7 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
     if (lane == 0) i = __hip_atomic_fetch_add(&q->seed_next, 1, __ATOMIC_RELAXED, AGENT);
     i = wave_bcast(i);
     if (i >= A.n) break;
-    if (ld_relaxed(&q->err) & kErrFatal) break;  // work already lost: stop seeding
+    if (ld_wave(&q->err) & kErrFatal) break;  // work already lost: stop seeding
     if (A.is[i].done != 0) continue;
     if (seed_limit(A, i, st, sm)) complete_limit(A, i, st, sm);
   }
@@ -712,8 +717,8 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
     uint16_t m;
     int cnt, inst;
     if (!q_take(A, ticket, t, th, m, cnt, inst)) {
-      if (ld_relaxed(&q->remaining) <= 0) break;
-      if (!A.server && (ld_relaxed(&q->err) & kErrFatal)) break;
+      if (ld_wave(&q->remaining) <= 0) break;
+      if (!A.server && (ld_wave(&q->err) & kErrFatal)) break;
       const uint64_t now = wall_clock64();
       // queue activity seen by this idle workgroup (lane 0's view)
       uint64_t act = 0;
@@ -761,8 +766,11 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
         sm[lane] = m;
       }
       WAVE_SYNC();
-      ok = run_unit<4, CAP, NPL>(A, inst, limit, st, sm, cnt, wc, tick, deadline, expanded, goals,
-                                 fmin);
+      ok = A.first_solution
+               ? run_unit<4, CAP, NPL, true>(A, inst, limit, st, sm, cnt, wc, tick, deadline,
+                                             expanded, goals, fmin)
+               : run_unit<4, CAP, NPL, false>(A, inst, limit, st, sm, cnt, wc, tick, deadline,
+                                              expanded, goals, fmin);
     } else if (width == 3) {
       if constexpr (CAP >= 256) {
         if (lane < cnt) {
@@ -770,8 +778,11 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
           sm[lane] = m;
         }
         WAVE_SYNC();
-        ok = run_unit<3, CAP, 64>(A, inst, limit, st, sm, cnt, wc, tick, deadline, expanded, goals,
-                                  fmin);
+        ok = A.first_solution
+                 ? run_unit<3, CAP, 64, true>(A, inst, limit, st, sm, cnt, wc, tick, deadline,
+                                              expanded, goals, fmin)
+                 : run_unit<3, CAP, 64, false>(A, inst, limit, st, sm, cnt, wc, tick, deadline,
+                                               expanded, goals, fmin);
       }
     } else {
       if constexpr (CAP / 2 >= 256) {
@@ -780,8 +791,11 @@ __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
           sm[lane] = m;
         }
         WAVE_SYNC();
-        ok = run_unit<5, CAP / 2, 64>(A, inst, limit, st5, sm, cnt, wc, tick, deadline, expanded,
-                                      goals, fmin);
+        ok = A.first_solution
+                 ? run_unit<5, CAP / 2, 64, true>(A, inst, limit, st5, sm, cnt, wc, tick,
+                                                  deadline, expanded, goals, fmin)
+                 : run_unit<5, CAP / 2, 64, false>(A, inst, limit, st5, sm, cnt, wc, tick,
+                                                   deadline, expanded, goals, fmin);
       }
     }
     if (!ok) break;
