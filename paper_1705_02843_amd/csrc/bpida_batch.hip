@@ -547,6 +547,11 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   const bool wide = W == 5;
   // largest growth of one round: a popped node has at most 4 children
   constexpr int kGrow = NPL == 16 ? 32 : 3 * 64;
+  // 64-node rounds on 3x3 and 4x4 stacks of 512+ entries store without
+  // branches: a lane that keeps no child writes it to the last entry, which
+  // never holds the stack
+  constexpr bool kTrash = NPL == 64 && CAP >= 512 && sizeof(S) == 8;
+  constexpr int kCap = kTrash ? CAP - 1 : CAP;
   const LaneMap M = make_lane_map(lane);
   // Donating from a shallow stack hands over pieces too small to pay for the
   // transfer; a threshold the stack seldom reaches stops donation and leaves
@@ -577,7 +582,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
           return false;
         }
       }
-      if (avail + kGrow <= CAP && avail >= dmin && (tick & A.donate_mask) == 0) {
+      if (avail + kGrow <= kCap && avail >= dmin && (tick & A.donate_mask) == 0) {
         // donation when workgroups wait on tickets no queued chunk covers:
         // the oldest min(window, avail) entries (the shallowest, largest
         // subtrees) are split alternately, so donor and receiver each keep
@@ -611,7 +616,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
         }
       }
     }
-    if (avail + kGrow > CAP) {
+    if (avail + kGrow > kCap) {
       // LDS could overflow: move the oldest entries to the queue, 64 at a
       // time, until the largest round fits.  One chunk is not always enough:
       // a 64-node round can add up to 128 entries (three children a node),
@@ -631,17 +636,17 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
         move_down(st, sm, 0u, 64u, top - 64u);
         top -= 64u;
         avail -= 64;
-      } while (avail + kGrow > CAP);
+      } while (avail + kGrow > kCap);
     }
     const int kp = min(avail, NPL);
     if constexpr (NPL == 16) {
       top = bp_round<CAP>((uint64_t*)st, sm, top, kp, limit, M, goals, fmin);
     } else {
-      top = bp_round64w<W, CAP>(st, sm, top, kp, goals);
+      top = bp_round64w<W, CAP, kTrash>(st, sm, top, kp, goals);
     }
     // the spill above keeps every round inside the ring; a round that ended
     // past it would have overwritten entries (reported, never silent)
-    if (top > (uint32_t)CAP) atomicOr(&q->err, 32);  // every lane: a uniform branch
+    if (top > (uint32_t)kCap) atomicOr(&q->err, 32);  // every lane: a uniform branch
     expanded += (uint64_t)kp;
     wc.rounds += 1;
     if constexpr (FS) {

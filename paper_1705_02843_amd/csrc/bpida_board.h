@@ -191,6 +191,13 @@ __device__ __forceinline__ uint32_t sel_lanes(uint64_t lm, uint32_t v) {
   return r;
 }
 
+// a where the lane's bit of m is set, else b (m read from scalar registers)
+__device__ __forceinline__ uint32_t sel_mask(uint64_t m, uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(m));
+  return r;
+}
+
 // Hides a value's known bits from the optimiser (no instruction is emitted).
 // Used where the compiler would otherwise re-derive one condition in two
 // forms, or keep a shift-amount mask the hardware applies anyway.
@@ -207,10 +214,11 @@ struct NodeCtx {
   uint32_t coli;   // horizontal moves: the blank's column (x W for width 4)
   uint32_t lmx;    // bit (A + 4 up): move A survives the f test
   uint32_t mbase;  // slack << 8 | blank
+  uint32_t trash;  // byte offset of the spare entry (branch-free stores)
 };
 
 // One move for every lane of a 64-node round (see bp_round64w).
-template <int W, int CAP, int A>
+template <int W, int CAP, int A, bool TRASH>
 __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm, uint32_t& out,
                                           const typename Board<W>::S s, const NodeCtx& c) {
   using B = Board<W>;
@@ -226,7 +234,10 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
   const uint32_t up = B::template up<A>(x, c.rowi, c.coli);
   const uint32_t kb = opaque((c.lmx >> (A + 4 * up)) & 1u);
   const uint64_t km = __builtin_amdgcn_uicmp(kb, 0u, 33);  // lanes with kb != 0
-  if (kb != 0u) {
+  // TRASH: every lane builds its child (a vector instruction costs the same
+  // for any number of active lanes) and the lanes that keep none store it to
+  // the spare entry, so the move needs no branch
+  if (TRASH || kb != 0u) {
     // successor: t moves from n to b, i.e. the packed word changes by
     // t * (base^b - base^n) = +/- (K * t) << (BITS * min(b, n))
     S cs;
@@ -249,7 +260,8 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
     // byte offsets into the stack: entry out + r (below CAP: the caller
     // leaves room for the largest round)
     constexpr uint32_t LS = sizeof(S) == 8 ? 3 : 4;
-    const uint32_t pst = (r + out) << LS;
+    uint32_t pst = (r + out) << LS;
+    if constexpr (TRASH) pst = sel_mask(km, pst, c.trash);
     *(S*)((char*)st + pst) = cs;
     *(uint16_t*)((char*)sm + (pst >> (LS - 1))) = (uint16_t)cm;
   }
@@ -259,12 +271,13 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
 // One BPDFS round with one popped node per lane, for any board width: pops
 // kp = min(64, top) nodes from a stack of entries [0, top), tests them for
 // the goal and pushes every legal, non-undoing child with f <= limit.  The
-// caller guarantees top + 3*kp <= CAP (no position wraps).  The
+// caller guarantees top + 3*kp <= CAP (CAP - 1 with TRASH, whose stores of
+// dropped children go to entry CAP - 1; no position wraps).  The
 // round does not track the f of pruned children: every slack on the stack is
 // even (f keeps the parity of h0, and so does the limit), so a child is
 // pruned only from slack 0, moving a tile away from its goal, and its f is
 // the limit + 2.
-template <int W, int CAP>
+template <int W, int CAP, bool TRASH>
 __device__ __forceinline__ uint32_t bp_round64w(typename Board<W>::S* st, uint16_t* sm, uint32_t top, int kp,
                                            int& goals) {
   using B = Board<W>;
@@ -298,11 +311,12 @@ __device__ __forceinline__ uint32_t bp_round64w(typename Board<W>::S* st, uint16
   c.rowi = B::row_part(c.b);
   c.coli = B::col_part(c.b);
   c.mbase = (m & 0xFF00u) | c.b;
+  c.trash = (uint32_t)(CAP - 1) << LS;
   uint32_t out = base;
-  bp_move_w<W, CAP, 0>(st, sm, out, s, c);
-  bp_move_w<W, CAP, 1>(st, sm, out, s, c);
-  bp_move_w<W, CAP, 2>(st, sm, out, s, c);
-  bp_move_w<W, CAP, 3>(st, sm, out, s, c);
+  bp_move_w<W, CAP, 0, TRASH>(st, sm, out, s, c);
+  bp_move_w<W, CAP, 1, TRASH>(st, sm, out, s, c);
+  bp_move_w<W, CAP, 2, TRASH>(st, sm, out, s, c);
+  bp_move_w<W, CAP, 3, TRASH>(st, sm, out, s, c);
   WAVE_SYNC();
   return out;
 }
