@@ -248,7 +248,7 @@ int bpida_server_stop(void);
  *                        alternately.  Overflow spills always move 64.
  *   "donate_min"         batched mode: smallest LDS stack (entries) that
  *                        donates (2..2048; -1 = four rounds' worth of pops,
- *                        at most half the ring: 256 for 64-node rounds, the
+ *                        at most half the stack: 256 for 64-node rounds, the
  *                        default).  Too small a value ships pieces of work
  *                        that cost more to move than they hold; one the stack
  *                        seldom reaches stops donation altogether.

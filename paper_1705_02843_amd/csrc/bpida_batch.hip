@@ -138,7 +138,7 @@ __device__ bool q_take(const BatchArgs& A, uint64_t& ticket, uint64_t& tile, uin
 // guard's release brought the instance's outstanding count to zero, i.e. the
 // caller must complete the limit itself.
 // `stage` (128 u64) and `stage_m` (64 u16) are LDS the caller does not use
-// while seeding (its stack ring is empty whenever a limit is seeded).
+// while seeding (its LDS stack is empty whenever a limit is seeded).
 __device__ bool seed_limit(const BatchArgs& A, int i, uint64_t* stage, uint16_t* stage_m) {
   const int lane = threadIdx.x;
   InstState* S = A.is + i;
@@ -399,7 +399,7 @@ __device__ void admitter_loop(const BatchArgs& A, uint64_t* st, uint16_t* sm, ui
   const int lane = threadIdx.x;
   const ServerArgs& V = A.srv;
   QueueCtl* q = A.q;
-  uint32_t* hist_lds = (uint32_t*)st;  // the ring is unused by the admitter
+  uint32_t* hist_lds = (uint32_t*)st;  // the stack is unused by the admitter
   uint64_t head = 0;
   int cursor = 0;
   for (;;) {
@@ -540,7 +540,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
                          uint16_t* sm, int cnt, WgCounters& wc, uint32_t& tick, uint64_t deadline,
                          uint64_t& expanded, int& goals, int& fmin) {
   static_assert(NPL == 64 || W == 4, "16-node rounds are the 4x4 map");
-  static_assert((CAP & (CAP - 1)) == 0 && CAP >= (NPL == 64 ? 256 : 128), "ring size");
+  static_assert((CAP & (CAP - 1)) == 0 && CAP >= (NPL == 64 ? 256 : 128), "stack size");
   using S = typename Board<W>::S;
   const int lane = threadIdx.x;
   QueueCtl* q = A.q;
@@ -556,7 +556,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   // Donating from a shallow stack hands over pieces too small to pay for the
   // transfer; a threshold the stack seldom reaches stops donation and leaves
   // subtrees on one workgroup.  Default: four rounds' worth of pops, at most
-  // half the ring.
+  // half the stack.
   const int dmin = A.donate_min > 0 ? A.donate_min : min(4 * NPL, CAP / 2);
   // The LDS stack holds entries [0, top), the oldest at 0.  Entries taken
   // from the bottom (spills, donations) make the rest move down, so a
@@ -644,7 +644,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
     } else {
       top = bp_round64w<W, CAP, kTrash>(st, sm, top, kp, goals);
     }
-    // the spill above keeps every round inside the ring; a round that ended
+    // the spill above keeps every round inside the stack; a round that ended
     // past it would have overwritten entries (reported, never silent)
     if (top > (uint32_t)kCap) atomicOr(&q->err, 32);  // every lane: a uniform branch
     expanded += (uint64_t)kp;
@@ -669,14 +669,14 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   return true;
 }
 
-// The persistent kernel.  LDS: a 10*CAP-byte ring, CAP entries of u64 tiles
+// The persistent kernel.  LDS: a 10*CAP-byte stack, CAP entries of u64 tiles
 // + u16 meta for widths 3 and 4, CAP/2 entries of 128-bit tiles + u16 meta
 // for width 5; the width is read per chunk from the instance.
 template <int CAP, int NPL>
 __global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
-  static_assert((CAP & (CAP - 1)) == 0 && CAP >= 128, "ring size");
+  static_assert((CAP & (CAP - 1)) == 0 && CAP >= 128, "stack size");
   static_assert(NPL == 16 || NPL == 64, "nodes per round");
-  static_assert(NPL == 16 || CAP >= 256, "ring too small for 64-node rounds");
+  static_assert(NPL == 16 || CAP >= 256, "stack too small for 64-node rounds");
   __shared__ __attribute__((aligned(16))) uint64_t lds[(10 * CAP) / 8];
   uint64_t* st = lds;                          // widths 3, 4: CAP tiles
   uint16_t* sm = (uint16_t*)(lds + CAP);       // CAP (or CAP/2) meta words
@@ -861,7 +861,7 @@ __global__ void batch_status_kernel(const InstState* __restrict__ is, int n,
   int32_t v = done;
   if (*split_err) v = -6;                    // BPIDA_EINTERNAL
   else if (q->err & kErrFatal) v = -4;      // BPIDA_ENOMEM
-  else if (q->err & 32) v = -6;             // LDS ring overrun: BPIDA_EINTERNAL
+  else if (q->err & 32) v = -6;             // LDS stack overrun: BPIDA_EINTERNAL
   else if (done == 0) v = -6;               // stopped by the watchdog or the deadline
   st[k] = v;
 }
@@ -1090,7 +1090,7 @@ static int occupancy_t() {
   return nb;
 }
 
-// Supported (ring capacity, nodes per round) pairs.
+// Supported (stack capacity, nodes per round) pairs.
 #define BATCH_CONFIGS(X) \
   X(128, 16) X(256, 16) X(512, 16) X(1024, 16) X(2048, 16) X(256, 64) X(512, 64) X(1024, 64) \
   X(2048, 64)
