@@ -86,15 +86,46 @@ def golden_total(parts):
     return tot
 
 
+def progress(msg):
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def cpu_model() -> str:
+    """The host CPU as lscpu names it (model name, family/model/stepping)."""
+    import subprocess
+    fields = {}
     try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            fields[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
         pass
-    return "unknown"
+    if not fields.get("Model name"):
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        fields["Model name"] = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    name = fields.get("Model name", "unknown")
+    extra = ", ".join("%s %s" % (k.lower(), fields[k]) for k in ("CPU family", "Model", "Stepping")
+                      if fields.get(k))
+    return "%s (%s)" % (name, extra) if extra else name
+
+
+def host_threads() -> tuple:
+    """(threads the oracle may use, the CPUs this process may run on, nproc).
+    The oracle takes every CPU of the process's affinity set, at most 16: a
+    one-GPU share of the host."""
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    return min(16, aff), aff, os.cpu_count() or 1
 
 
 def cpu_baseline(parts, budget_nodes, nthreads, single_nodes=2.5e8):
@@ -225,7 +256,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2_md30_38", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c3_uneven", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget-nodes", type=float, default=4e9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="batched", choices=sorted(MODES),
@@ -233,6 +264,8 @@ def main():
                          "work queue; plain: one launch per instance and f-limit)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip timing the other mode beside it")
+    ap.add_argument("--compare-steps", type=int, default=3,
+                    help="timed steps of the other mode (median reported; one warm-up step first)")
     ap.add_argument("--untuned", action="store_true",
                     help="ignore the autotuner's table (paper_1705_02843_amd/tuning/) and use the "
                          "library defaults")
@@ -310,6 +343,7 @@ def main():
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
+        progress("%s: %d warm-up step(s) done" % (mode, warmup))
         acc = {}
         per_step = []
         t0 = time.perf_counter()
@@ -317,6 +351,7 @@ def main():
             ts = time.perf_counter()
             step()  # returns once the results are in device memory
             per_step.append(time.perf_counter() - ts)
+            progress("%s: step %d of %d, %.3f s" % (mode, len(per_step), steps, per_step[-1]))
             for k, v in bpida.last_stats().items():
                 acc[k] = acc.get(k, 0) + v
         torch.cuda.synchronize()
@@ -389,7 +424,7 @@ def main():
                                                 "lds_bank_conflict_cycles", "waves_per_simd")
                       if k in counters} if counters else None),
         "search_rounds_per_step": rounds // max(1, args.steps),
-        "pop_occupancy": round(search_nodes / (16.0 * rounds), 4) if rounds else None,
+        "pop_occupancy": round(search_nodes / (float(npl) * rounds), 4) if rounds else None,
         "kernel_source_hash": src_hash,
     }
     if args.mode == "batched" and wg_total:
@@ -397,19 +432,20 @@ def main():
                           "busy_frac": round(acc["wg_us_search"] / wg_total, 4),
                           "queue_frac": round(acc["wg_us_queue"] / wg_total, 4),
                           "chunks_donated_per_step": acc["chunks_pushed"] // max(1, args.steps)}
-    if not args.no_compare and n > 512:
-        out["compare"] = {"skipped": "plain path not timed on batches above 512 states"}
-    elif not args.no_compare:
+    if not args.no_compare and widths is None:
         other = "plain" if args.mode == "batched" else "batched"
         saved = {k: bpida.get_option(k) for k in ("frontier_depth", "lds_stack_capacity",
                                                   "max_workgroups")}
-        odt, _, _ = run_mode(other, 1, 1)
+        _, _, oacc = run_mode(other, args.compare_steps, 1)
         for k, v in saved.items():
             bpida.set_option(k, v)
+        odt = oacc["median_step_s"]
         out["compare"] = {"mode": other, "value": round(nodes_per_step / odt, 1),
-                          "unit": "nodes/s", "ms_per_step": round(odt * 1e3, 3),
-                          "instances_per_s": round(n / odt, 2), "steps": 1, "warmup": 1,
-                          "speedup_of_value": round((nodes_per_step / odt) and value / (nodes_per_step / odt), 3)}
+                          "unit": "nodes/s", "ms_per_step_median": round(odt * 1e3, 3),
+                          "instances_per_s": round(n / odt, 2), "steps": args.compare_steps,
+                          "warmup": 1,
+                          "speedup_of_instances_per_s": round(
+                              (n * args.steps / dt) / (n / odt), 3)}
         bpida.set_option("mode", MODES[args.mode])
     if args.mode == "batched" and not args.kernel_only:
         # the host-buffer entry (PCIe copies in and out included), beside `value`
@@ -434,8 +470,10 @@ def main():
         out["first_solution"] = first_solution_leg(bpida, parts[0], states, width, d_states, d_len,
                                                    d_nodes, stream, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
-        nthreads = min(16, os.cpu_count() or 1)
+        nthreads, aff, nproc = host_threads()
+        progress("oracle on %d host threads" % nthreads)
         out["cpu_baseline"] = cpu_baseline(parts, args.cpu_budget_nodes, nthreads)
+        out["cpu_baseline"]["host_cpus"] = {"affinity": aff, "nproc": nproc}
     print(json.dumps(out), flush=True)
 
 
