@@ -165,7 +165,8 @@ int bpida_server_submit(const uint8_t *state, uint64_t *ticket);
 /*
  * Collect the answer of `ticket`: returns 1 and fills out_len, out_nodes
  * (host, BPIDA_MAX_THRESHOLDS uint64 as in bpida_solve) and status (1 solved,
- * else a negative bpida_status) once it is ready; 0 while it is pending;
+ * else a negative bpida_status; BPIDA_ENOMEM if the work queue overflowed
+ * while this request was searched, its length then -1) once it is ready; 0 while it is pending;
  * BPIDA_EINVAL for an unknown or already collected ticket.  Answers stay
  * readable after bpida_server_stop until the next bpida_server_start.
  */
@@ -199,8 +200,18 @@ int bpida_server_stop(void);
  *                        overflow the default work queue (BPIDA_ENOMEM)
  *   "nodes_per_round"    batched mode: 64 (default) pops one node per lane and
  *                        each lane tries the four moves; 16 uses Alg. 1's map
- *                        (lane l expands node l/4 with move l%4).  Plain mode
- *                        always uses 16.
+ *                        (lane l expands node l/4 with move l%4).
+ *   "wg_size"            batched mode and server: threads per workgroup of the
+ *                        persistent kernel, 64 (default), 128 or 256: 1, 2 or
+ *                        4 waves, each with its own LDS stack, taking its own
+ *                        work and never waiting for the others (Sec. 5's
+ *                        block = one warp, several per workgroup); 128 and 256
+ *                        need 64-node rounds and a stack of 512+ entries.
+ *                        Results do not depend on it.
+ *   "plain_nodes_per_round"
+ *                        plain mode: 16 (default, Alg. 1's map) or 64 (the
+ *                        batched kernel's round: one node per lane; needs an
+ *                        LDS stack of at least 512 entries, default 1024)
  *   "spill_capacity"     plain mode: per-workgroup HBM spill entries, a
  *                        multiple of 64 (default 16384)
  *   "queue_capacity"     batched mode: queue slots of 64 entries (rounded up
@@ -252,6 +263,14 @@ int bpida_server_stop(void);
  *                        default).  Too small a value ships pieces of work
  *                        that cost more to move than they hold; one the stack
  *                        seldom reaches stops donation altogether.
+ *   "push_spin"          batched mode and server: polls (of about 64 clocks
+ *                        each) a push waits for a full work-queue slot before
+ *                        it gives up and the pushed entries are lost (1..2^24,
+ *                        default 65536).  A small value makes a full queue
+ *                        lose work at once: a batched call then reports
+ *                        BPIDA_ENOMEM, and the server answers each request
+ *                        that lost work with status BPIDA_ENOMEM (never with
+ *                        counts short of the true ones) and keeps serving.
  * Returns BPIDA_OK, or BPIDA_EINVAL for an unknown key or a bad value.
  */
 int bpida_set_option(const char *key, int64_t value);

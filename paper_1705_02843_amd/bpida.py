@@ -17,7 +17,8 @@ OK, EINVAL, EUNSOLVABLE, ELIMIT, ENOMEM, EDEVICE, EINTERNAL, EAGAIN = 0, -1, -2,
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbpida.so")
 
-EXPORTS = ("bpida_solve", "bpida_solve_mixed", "bpida_solve_mixed_device", "bpida_solve_device", "bpida_solve_device_async", "bpida_set_option",
+EXPORTS = ("bpida_solve", "bpida_solve_mixed", "bpida_solve_mixed_device", "bpida_solve_device",
+           "bpida_solve_device_async", "bpida_set_option",
            "bpida_get_option", "bpida_last_stats", "bpida_strerror", "bpida_server_start",
            "bpida_server_submit", "bpida_server_poll", "bpida_server_stop")
 
@@ -32,6 +33,15 @@ def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError("libbpida.so is not built; run `python -m paper_1705_02843_amd.build` "
                           "(or __graft_entry__.build())")
+    # PyTorch ships its own HIP runtime, which its libraries load under a
+    # name the dynamic linker does not match against an already loaded
+    # ROCm copy: loading libbpida.so (which needs libamdhip64.so.7) first
+    # would leave two HIP runtimes in the process, and torch's device copies
+    # then crash.  Importing torch first makes the library bind to torch's.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     lib.bpida_solve.argtypes = [P(ctypes.c_uint8), ctypes.c_int32, ctypes.c_int32,

@@ -25,6 +25,16 @@ namespace bpida {
 
 #define AGENT __HIP_MEMORY_SCOPE_AGENT
 
+// The split kernels' level sizes, built at compile time.
+__device__ WalkTable g_walk_table = make_walk_table();
+
+hipError_t walk_table_device(const int32_t** out) {
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_walk_table));
+  *out = static_cast<const int32_t*>(p);
+  return e;
+}
+
 __device__ __forceinline__ uint64_t ld_relaxed(uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, AGENT);
 }
@@ -40,18 +50,26 @@ __device__ __forceinline__ int32_t ld_wave(int32_t* p) {
 
 // ---------------------------------------------------------------------------
 // Ticket queue of chunks.  Producers and consumers take tickets with a
-// fetch-and-add on tail / head (no compare-and-swap loops, which collapse
-// under thousands of contending workgroups).  Slot k of the ring carries a
-// sequence number: seq == t means "free for producer ticket t", seq == t + 1
-// means "holds the chunk of ticket t".  An idle workgroup takes one consumer
-// ticket and then polls only its own slot, so waiting workgroups do not
-// contend on a shared line; head - tail = waiting workgroups - queued chunks,
-// which is what a busy workgroup reads to decide whether to donate.  Every
-// operation is done by a whole wave: lane 0 handles tickets, all lanes move
-// the 64 entries.
+// fetch-and-add on tail / head (no compare-and-swap loops on those two
+// counters, which collapse under thousands of contending workgroups).  Slot
+// k of the ring carries the state of ticket t = the next ticket to use it:
+// 4t free for producer t, 4t + 1 claimed by producer t (being written),
+// 4t + 2 holds the chunk of ticket t.  An idle wave takes one consumer ticket
+// and then polls only its own slot, so waiting waves do not contend on a
+// shared line; head - tail = waiting waves - queued chunks, which is what a
+// busy wave reads to decide whether to donate.  Every operation is done by a
+// whole wave: lane 0 handles tickets, all lanes move the 64 entries.
+//
+// A producer whose slot is still occupied after A.push_spin polls gives its
+// ticket up and raises the slot's `abandoned` mark to at least t + 1.  A
+// consumer holding ticket t whose slot is free for t while the mark is past
+// t hands the slot on to ticket t + capacity with a compare-and-swap (the
+// producer claims it with one too, so exactly one of them wins; a late
+// producer that loses gives up as well).  A lost ticket therefore never
+// strands a consumer and the ring keeps working; the lost chunk's work is
+// gone, its instance is marked lost and the call reports BPIDA_ENOMEM.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kNoTicket = ~0ull;
-constexpr int kPushSpin = 1 << 16;  // bounded wait for a slot still being read
 
 __device__ __forceinline__ uint64_t bcast64(uint64_t v) {
   const uint32_t lo = (uint32_t)wave_bcast((int)(uint32_t)v);
@@ -59,11 +77,17 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Returns false only if the ring stayed full for the whole bounded wait.
-// `hi` is stored only for 5x5 chunks (wide).
+__device__ __forceinline__ bool cas64(uint64_t* p, uint64_t expect, uint64_t want) {
+  return __hip_atomic_compare_exchange_strong(p, &expect, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                              AGENT);
+}
+
+// Returns false if the ring stayed full for the whole bounded wait (the
+// entries were not queued).  `hi` is stored only for 5x5 chunks (wide), in
+// the slot's row of A.hi.
 __device__ bool q_push(const BatchArgs& A, uint64_t tile, uint64_t hi, uint16_t meta, int count,
                        int inst, bool wide) {
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   QueueCtl* q = A.q;
   const uint64_t mask = A.qmask;
   uint64_t pos = 0;
@@ -72,59 +96,74 @@ __device__ bool q_push(const BatchArgs& A, uint64_t tile, uint64_t hi, uint16_t 
     pos = __hip_atomic_fetch_add(&q->tail, (uint64_t)1, __ATOMIC_RELAXED, AGENT);
     const uint64_t h = ld_relaxed(&q->head);
     if (pos + 1 > h) __hip_atomic_fetch_max(&q->qmax, pos + 1 - h, __ATOMIC_RELAXED, AGENT);
-    for (int k = 0; k < kPushSpin; ++k) {
-      if (ld_relaxed(&A.seq[pos & mask]) == pos) {
-        ok = 1;
+    SlotCtl* sc = A.seq + (pos & mask);
+    for (int k = 0; k < A.push_spin; ++k) {
+      const uint64_t v = ld_relaxed(&sc->seq);
+      if (v == 4 * pos) {
+        ok = cas64(&sc->seq, 4 * pos, 4 * pos + 1) ? 1 : 0;
         break;
       }
+      if (v > 4 * pos) break;  // handed on past this ticket by its consumer
       __builtin_amdgcn_s_sleep(1);
+    }
+    if (!ok) {
+      __hip_atomic_fetch_max(&sc->abandoned, pos + 1, __ATOMIC_RELAXED, AGENT);
+      atomicOr(&q->err, 16);  // ticket lost: the call reports BPIDA_ENOMEM
     }
   }
   ok = wave_bcast(ok);
-  if (!ok) {
-    if (lane == 0) atomicOr(&q->err, 16);  // ticket lost: the call reports BPIDA_ENOMEM
-    return false;
-  }
+  if (!ok) return false;
   pos = bcast64(pos);
   // the slot's previous consumer released it; order the new payload after
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   QChunk* c = A.slots + (pos & mask);
   c->tiles[lane] = tile;
-  if (wide) c->hi[lane] = hi;
+  if (wide) A.hi[(pos & mask) * kQChunk + lane] = hi;
   c->meta[lane] = meta;
   if (lane == 0) {
     c->inst = inst;
     c->count = count;
+    c->wide = wide ? 1 : 0;
   }
-  __syncthreads();  // one-wave workgroup: every lane's stores precede lane 0's release
-  if (lane == 0) __hip_atomic_store(&A.seq[pos & mask], pos + 1, __ATOMIC_RELEASE, AGENT);
+  WAVE_SYNC_MEM();  // every lane's stores precede lane 0's release
+  if (lane == 0) __hip_atomic_store(&A.seq[pos & mask].seq, 4 * pos + 2, __ATOMIC_RELEASE, AGENT);
   return true;
 }
 
 // Takes a consumer ticket if `ticket` holds none, then checks whether that
 // ticket's chunk has arrived.  Returns true with the chunk, or false (the
-// ticket is kept for the next call).
+// ticket is kept for the next call, or dropped if its producer gave up).
 __device__ bool q_take(const BatchArgs& A, uint64_t& ticket, uint64_t& tile, uint64_t& hi,
                        uint16_t& meta, int& count, int& inst) {
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   QueueCtl* q = A.q;
   const uint64_t mask = A.qmask;
   int ready = 0;
   if (lane == 0) {
     if (ticket == kNoTicket) ticket = __hip_atomic_fetch_add(&q->head, (uint64_t)1, __ATOMIC_RELAXED, AGENT);
-    ready = ld_relaxed(&A.seq[ticket & mask]) == ticket + 1;
+    SlotCtl* sc = A.seq + (ticket & mask);
+    const uint64_t v = ld_relaxed(&sc->seq);
+    ready = v == 4 * ticket + 2;
+    if (!ready && v == 4 * ticket && ld_relaxed(&sc->abandoned) > ticket &&
+        cas64(&sc->seq, 4 * ticket, 4 * (ticket + mask + 1))) {
+      // a producer of this slot gave up at or after this ticket: hand the
+      // slot on and take a new ticket next time
+      ticket = kNoTicket;
+    }
   }
   ticket = bcast64(ticket);
   if (!wave_bcast(ready)) return false;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const QChunk* c = A.slots + (ticket & mask);
   tile = c->tiles[lane];
-  hi = c->hi[lane];
   meta = c->meta[lane];
   count = wave_bcast(c->count);
   inst = wave_bcast(c->inst);
-  __syncthreads();  // all lanes have read the slot before it is handed back
-  if (lane == 0) __hip_atomic_store(&A.seq[ticket & mask], ticket + mask + 1, __ATOMIC_RELEASE, AGENT);
+  // the high words only for a 5x5 chunk: a 4x4 chunk reads 6 lines, not 10
+  hi = wave_bcast(c->wide) ? A.hi[(ticket & mask) * kQChunk + lane] : 0ull;
+  WAVE_SYNC_MEM();  // all lanes have read the slot before it is handed back
+  if (lane == 0)
+    __hip_atomic_store(&A.seq[ticket & mask].seq, 4 * (ticket + mask + 1), __ATOMIC_RELEASE, AGENT);
   ticket = kNoTicket;
   return true;
 }
@@ -140,7 +179,7 @@ __device__ bool q_take(const BatchArgs& A, uint64_t& ticket, uint64_t& tile, uin
 // `stage` (128 u64) and `stage_m` (64 u16) are LDS the caller does not use
 // while seeding (its LDS stack is empty whenever a limit is seeded).
 __device__ bool seed_limit(const BatchArgs& A, int i, uint64_t* stage, uint16_t* stage_m) {
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   InstState* S = A.is + i;
   const int L = S->limit;
   const bool wide = S->width == 5;
@@ -189,6 +228,7 @@ __device__ bool seed_limit(const BatchArgs& A, int i, uint64_t* stage, uint16_t*
         full = true;  // the remaining roots are dropped; the call reports BPIDA_ENOMEM
         if (lane == 0) {
           __hip_atomic_fetch_add(&S->outstanding, -1, __ATOMIC_RELAXED, AGENT);
+          __hip_atomic_store(&S->lost, 1, __ATOMIC_RELAXED, AGENT);
           atomicOr(&A.q->err, 1);
         }
       }
@@ -207,9 +247,9 @@ __device__ bool seed_limit(const BatchArgs& A, int i, uint64_t* stage, uint16_t*
 // Server mode: copy slot i's answer into the pinned result ring, publish it,
 // and free the slot.  Executed by one wave after the slot's outputs are final.
 __device__ void emit_result(const BatchArgs& A, int i, int status) {
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   const ServerArgs& V = A.srv;
-  __syncthreads();  // the slot's output row, written by lane 0, is visible
+  WAVE_SYNC_MEM();  // the slot's output row, written by lane 0, is visible
   const uint64_t t = V.ticket[i];
   ServerRes* r = V.res + (t & V.ring_mask);
   r->nodes[lane] = A.out_nodes[(size_t)i * 64 + lane];
@@ -217,7 +257,7 @@ __device__ void emit_result(const BatchArgs& A, int i, int status) {
     r->len = A.out_len[i];
     r->status = status;
   }
-  __syncthreads();
+  WAVE_SYNC_MEM();
   if (lane == 0) {
     __hip_atomic_store(&r->seq, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(&V.busy[i], 0, __ATOMIC_RELEASE, AGENT);
@@ -229,7 +269,7 @@ __device__ void emit_result(const BatchArgs& A, int i, int status) {
 // and this wave observed it), then advances it.  Loops while a new limit
 // has no queued work.
 __device__ void complete_limit(const BatchArgs& A, int i, uint64_t* stage, uint16_t* stage_m) {
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   InstState* S = A.is + i;
   for (;;) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -252,7 +292,9 @@ __device__ void complete_limit(const BatchArgs& A, int i, uint64_t* stage, uint1
       A.out_nodes[(size_t)i * 64 + col] = total;
       const int goals = ld_relaxed(&S->goals);
       const int fnext = min(fm, ld_relaxed(&S->fmin));
-      if (goals > 0 || A.goal_g[i] <= L) {
+      if (ld_relaxed(&S->lost)) {
+        state = -4;  // BPIDA_ENOMEM: work of this limit was dropped, its counts are void
+      } else if (goals > 0 || A.goal_g[i] <= L) {
         A.out_len[i] = L;
         state = 1;
       } else if (fnext != L + 2) {
@@ -276,7 +318,7 @@ __device__ void complete_limit(const BatchArgs& A, int i, uint64_t* stage, uint1
       if (A.server) emit_result(A, i, state);
       return;
     }
-    __syncthreads();
+    WAVE_SYNC_MEM();
     if (!seed_limit(A, i, stage, stage_m)) return;
   }
 }
@@ -287,7 +329,7 @@ __device__ void complete_limit(const BatchArgs& A, int i, uint64_t* stage, uint1
 
 // Validate and pack a state of 16 bytes (in pinned host memory) with one wave.
 __device__ Inst wave_ingest4(const uint8_t* src) {
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   const uint32_t v = lane < 16 ? (uint32_t)src[lane] : 0u;
   // permutation: every value 0..15 exactly once
   uint32_t seen = lane < 16 && v < 16 ? (1u << v) : 0u;
@@ -331,7 +373,7 @@ __device__ Inst wave_ingest4(const uint8_t* src) {
 // walks[blank][depth].
 __device__ int64_t wave_split4(const Inst& I, int depth, const int32_t* walks, NodeW* base,
                                uint32_t* hist_lds, uint32_t* hist_out, int32_t* goal_g_out) {
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   for (int k = lane; k < kHistBins; k += 64) hist_lds[k] = 0;
   if (lane == 0) {
     NodeW r;
@@ -341,7 +383,7 @@ __device__ int64_t wave_split4(const Inst& I, int depth, const int32_t* walks, N
     r.f = (uint32_t)I.h0;
     base[0] = r;
   }
-  __syncthreads();
+  WAVE_SYNC_MEM();
   const int32_t* lc = walks + (size_t)I.blank * (kMaxDepth + 1);
   int gmin = INT_MAX;
   int64_t lvl = 0;
@@ -384,19 +426,19 @@ __device__ int64_t wave_split4(const Inst& I, int depth, const int32_t* walks, N
         fill += __popcll(km);
       }
     }
-    __syncthreads();  // this level's children are visible to the whole wave
+    WAVE_SYNC_MEM();  // this level's children are visible to the whole wave
     lvl = next;
   }
   gmin = wave_min(gmin);
   for (int k = lane; k < kHistBins; k += 64) hist_out[k] = hist_lds[k];
   if (lane == 0) *goal_g_out = gmin;
-  __syncthreads();
+  WAVE_SYNC_MEM();
   return lvl;
 }
 
 // Admits requests until the host asks to stop and nothing is in flight.
 __device__ void admitter_loop(const BatchArgs& A, uint64_t* st, uint16_t* sm, uint64_t deadline) {
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   const ServerArgs& V = A.srv;
   QueueCtl* q = A.q;
   uint32_t* hist_lds = (uint32_t*)st;  // the stack is unused by the admitter
@@ -465,6 +507,7 @@ __device__ void admitter_loop(const BatchArgs& A, uint64_t* st, uint16_t* sm, ui
     S.fmin = INT_MAX;
     S.goals = 0;
     S.stop = 0;
+    S.lost = 0;
     S.root_off = (int64_t)slot * V.stride;
     S.nroots = 0;
     S.width = 4;
@@ -478,7 +521,7 @@ __device__ void admitter_loop(const BatchArgs& A, uint64_t* st, uint16_t* sm, ui
       if (S.limit > A.max_limit) S.done = -3;  // BPIDA_ELIMIT
     }
     if (lane == 0) A.is[slot] = S;
-    __syncthreads();
+    WAVE_SYNC_MEM();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (S.done != 0) emit_result(A, slot, S.done);
     else if (seed_limit(A, slot, st, sm)) complete_limit(A, slot, st, sm);
@@ -490,7 +533,7 @@ __device__ void admitter_loop(const BatchArgs& A, uint64_t* st, uint16_t* sm, ui
 // releases the unit; completes the limit if it was the last unit.
 __device__ void release_unit(const BatchArgs& A, int i, uint64_t expanded, int goals, int fmin,
                              uint64_t* stage, uint16_t* stage_m) {
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   InstState* S = A.is + i;
   fmin = wave_min(fmin);
   int last = 0;
@@ -511,24 +554,6 @@ struct WgCounters {
   uint64_t rounds = 0, pushes = 0, voluntary = 0;
 };
 
-// Moves LDS stack entries [src, src + n) down to [dst, dst + n), dst < src,
-// 64 at a time in ascending order: every entry is read before anything is
-// written over it.
-template <typename S>
-__device__ __forceinline__ void move_down(S* st, uint16_t* sm, uint32_t dst, uint32_t src, uint32_t n) {
-  const uint32_t lane = threadIdx.x;
-  for (uint32_t i = 0; i < n; i += 64u) {
-    const uint32_t k = i + lane;
-    if (k < n) {
-      const S t = st[src + k];
-      const uint16_t m = sm[src + k];
-      st[dst + k] = t;
-      sm[dst + k] = m;
-    }
-  }
-  WAVE_SYNC();
-}
-
 // Searches one unit (the chunk already in LDS entries [0, cnt)) of an
 // instance of width W until its stack is empty: BPDFS rounds, with spills
 // to the queue when LDS would overflow and donations to waiting workgroups.
@@ -542,7 +567,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   static_assert(NPL == 64 || W == 4, "16-node rounds are the 4x4 map");
   static_assert((CAP & (CAP - 1)) == 0 && CAP >= (NPL == 64 ? 256 : 128), "stack size");
   using S = typename Board<W>::S;
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   QueueCtl* q = A.q;
   const bool wide = W == 5;
   // largest growth of one round: a popped node has at most 4 children
@@ -631,6 +656,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
           wc.pushes += 1;
         } else if (lane == 0) {
           __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
+          __hip_atomic_store(&A.is[inst].lost, 1, __ATOMIC_RELAXED, AGENT);
           atomicOr(&q->err, 2);  // entries dropped: the call reports BPIDA_ENOMEM
         }
         move_down(st, sm, 0u, 64u, top - 64u);
@@ -669,19 +695,24 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   return true;
 }
 
-// The persistent kernel.  LDS: a 10*CAP-byte stack, CAP entries of u64 tiles
-// + u16 meta for widths 3 and 4, CAP/2 entries of 128-bit tiles + u16 meta
-// for width 5; the width is read per chunk from the instance.
-template <int CAP, int NPL>
-__global__ __launch_bounds__(64) void batch4_kernel(BatchArgs A) {
+// The persistent kernel.  A workgroup holds WPG independent waves (Sec. 5's
+// block = one warp, WPG times over): each wave has its own stack and takes
+// its own work, and no wave ever waits for another.  LDS per wave: a
+// 10*CAP-byte stack, CAP entries of u64 tiles + u16 meta for widths 3 and 4,
+// CAP/2 entries of 128-bit tiles + u16 meta for width 5; the width is read
+// per chunk from the instance.
+template <int CAP, int NPL, int WPG>
+__global__ __launch_bounds__(64 * WPG) void batch4_kernel(BatchArgs A) {
   static_assert((CAP & (CAP - 1)) == 0 && CAP >= 128, "stack size");
   static_assert(NPL == 16 || NPL == 64, "nodes per round");
   static_assert(NPL == 16 || CAP >= 256, "stack too small for 64-node rounds");
-  __shared__ __attribute__((aligned(16))) uint64_t lds[(10 * CAP) / 8];
-  uint64_t* st = lds;                          // widths 3, 4: CAP tiles
-  uint16_t* sm = (uint16_t*)(lds + CAP);       // CAP (or CAP/2) meta words
-  unsigned __int128* st5 = (unsigned __int128*)lds;  // width 5: CAP/2 tiles
-  const int lane = threadIdx.x;
+  static_assert(WPG == 1 || WPG == 2 || WPG == 4, "waves per workgroup");
+  constexpr int kWords = (10 * CAP) / 8;  // u64 words of one wave's stack
+  __shared__ __attribute__((aligned(16))) uint64_t lds[WPG * kWords];
+  uint64_t* st = lds + (WPG == 1 ? 0 : (int)(threadIdx.x >> 6) * kWords);  // widths 3, 4: CAP tiles
+  uint16_t* sm = (uint16_t*)(st + CAP);        // CAP (or CAP/2) meta words
+  unsigned __int128* st5 = (unsigned __int128*)st;  // width 5: CAP/2 tiles
+  const int lane = lane_id();
   QueueCtl* q = A.q;
 
   if (A.server) {
@@ -829,7 +860,10 @@ __global__ void batch_setup_kernel(BatchArgs A, const InstW* __restrict__ inst,
                                    const int64_t* __restrict__ root_off,
                                    const int32_t* __restrict__ nroots) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k <= (int64_t)A.qmask) A.seq[k] = (uint64_t)k;
+  if (k <= (int64_t)A.qmask) {
+    A.seq[k].seq = 4 * (uint64_t)k;
+    A.seq[k].abandoned = 0;
+  }
   if (k < A.n) {
     InstState S;
     S.limit = first_limit(inst[k].h0, A.start_limit);
@@ -840,6 +874,7 @@ __global__ void batch_setup_kernel(BatchArgs A, const InstW* __restrict__ inst,
     S.fmin = INT_MAX;
     S.goals = 0;
     S.stop = 0;
+    S.lost = 0;
     S.root_off = root_off[k];
     S.nroots = nroots[k];
     S.width = inst[k].width;
@@ -1045,7 +1080,10 @@ hipError_t launch_splitw(const InstW* d_inst, int n, int depth, const int64_t* d
 // `remaining` (cleared by the admitter when the server shuts down).
 __global__ void server_setup_kernel(BatchArgs A) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k <= (int64_t)A.qmask) A.seq[k] = (uint64_t)k;
+  if (k <= (int64_t)A.qmask) {
+    A.seq[k].seq = 4 * (uint64_t)k;
+    A.seq[k].abandoned = 0;
+  }
   if (k < A.srv.slots) A.srv.busy[k] = 0;
   if (k == 0) {
     A.q->remaining = 1;
@@ -1076,37 +1114,39 @@ hipError_t launch_batch_status(const InstState* d_is, int n, const QueueCtl* d_q
   return hipGetLastError();
 }
 
-template <int CAP, int NPL>
+template <int CAP, int NPL, int WPG>
 static hipError_t launch_batch_t(int grid, const BatchArgs& A, hipStream_t s) {
-  hipLaunchKernelGGL((batch4_kernel<CAP, NPL>), dim3(grid), dim3(64), 0, s, A);
+  hipLaunchKernelGGL((batch4_kernel<CAP, NPL, WPG>), dim3(grid), dim3(64 * WPG), 0, s, A);
   return hipGetLastError();
 }
 
-template <int CAP, int NPL>
+template <int CAP, int NPL, int WPG>
 static int occupancy_t() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch4_kernel<CAP, NPL>, 64, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch4_kernel<CAP, NPL, WPG>, 64 * WPG, 0) !=
+      hipSuccess)
     return 0;
   return nb;
 }
 
-// Supported (stack capacity, nodes per round) pairs.
-#define BATCH_CONFIGS(X) \
-  X(128, 16) X(256, 16) X(512, 16) X(1024, 16) X(2048, 16) X(256, 64) X(512, 64) X(1024, 64) \
-  X(2048, 64)
+// Supported (stack capacity, nodes per round, waves per workgroup) triples.
+#define BATCH_CONFIGS(X)                                                                         \
+  X(128, 16, 1) X(256, 16, 1) X(512, 16, 1) X(1024, 16, 1) X(2048, 16, 1) X(256, 64, 1)          \
+  X(512, 64, 1) X(1024, 64, 1) X(2048, 64, 1) X(512, 64, 2) X(1024, 64, 2) X(2048, 64, 2)        \
+  X(512, 64, 4) X(1024, 64, 4) X(2048, 64, 4)
 
-hipError_t launch_batch4(int lds_cap, int npl, int grid, const BatchArgs& A, hipStream_t s) {
+hipError_t launch_batch4(int lds_cap, int npl, int wpg, int grid, const BatchArgs& A, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-#define X(C, N) \
-  if (lds_cap == C && npl == N) return launch_batch_t<C, N>(grid, A, s);
+#define X(C, N, G) \
+  if (lds_cap == C && npl == N && wpg == G) return launch_batch_t<C, N, G>(grid, A, s);
   BATCH_CONFIGS(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-int batch4_max_blocks_per_cu(int lds_cap, int npl) {
-#define X(C, N) \
-  if (lds_cap == C && npl == N) return occupancy_t<C, N>();
+int batch4_max_blocks_per_cu(int lds_cap, int npl, int wpg) {
+#define X(C, N, G) \
+  if (lds_cap == C && npl == N && wpg == G) return occupancy_t<C, N, G>();
   BATCH_CONFIGS(X)
 #undef X
   return 0;

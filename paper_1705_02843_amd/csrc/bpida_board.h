@@ -282,7 +282,7 @@ __device__ __forceinline__ uint32_t bp_round64w(typename Board<W>::S* st, uint16
                                            int& goals) {
   using B = Board<W>;
   using S = typename B::S;
-  const int lane = threadIdx.x;
+  const int lane = lane_id();
   const uint32_t base = top - (uint32_t)kp;
   constexpr uint32_t LS = sizeof(S) == 8 ? 3 : 4;
   const uint32_t pst = (base + (uint32_t)lane) << LS;

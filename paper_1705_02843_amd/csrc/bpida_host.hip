@@ -42,6 +42,9 @@ struct Options {
   int64_t static_lb = 1;       // plain mode: re-split heavy roots between limits (Sec. 5)
   int64_t start_threshold = -1; // first f-limit to search (-1: h0)
   int64_t seed_chunk = 64;      // batched mode: roots per seeded chunk (8, 16, 32, 64)
+  int64_t push_spin = 65536;    // batched mode: polls of a full queue slot before a push gives up
+  int64_t plain_nodes_per_round = 16;  // plain mode: 16 (Alg. 1's lane map) or 64
+  int64_t wg_size = 64;         // batched mode: threads per workgroup (1, 2 or 4 independent waves)
 };
 
 std::mutex g_mu;  // serialises solves and option changes
@@ -87,9 +90,11 @@ struct Workspace {
   bool arch_ok = false;
   uint64_t qcap = 0;  // queue slots of the last batched launch
   DevBuf inst, tree, tree_off, hist, goal_g, err, cursor, part, spill_t, spill_m, res, stop;
-  DevBuf qctl, qseq, qslots, istate, root_off, nroots, status, walks;
-  // non-backtracking walk counts per width (3, 4, 5), start cell and length
-  int32_t h_walks[3][kWalkCells][kMaxDepth + 1];
+  DevBuf qctl, qseq, qslots, qhi, istate, root_off, nroots, status;
+  // non-backtracking walk counts per width (3, 4, 5), start cell and length:
+  // the device table (d_walks) and its host copy
+  const int32_t* d_walks = nullptr;
+  WalkTable h_walks = make_walk_table();
   DevBuf treew, winst, tree_offw, widths, byte_off;
   DevBuf h2d_states, out_len, out_nodes;
   DevBuf lb_load, lb_roots[2], lb_level, lb_count, lb_off, lb_avg, lb_total;
@@ -106,31 +111,10 @@ int map_err(hipError_t e) {
 }
 
 // Number of non-backtracking blank walks of each length 0..depth from cell
-// `blank` of a width-w board (the exact size of each split-tree level).
-void level_sizes_w(int w, int blank, int depth, int32_t* out) {
-  int64_t cur[kWalkCells][5] = {};
-  cur[blank][4] = 1;
-  for (int d = 0; d <= depth; ++d) {
-    int64_t tot = 0, nxt[kWalkCells][5] = {};
-    for (int c = 0; c < w * w; ++c)
-      for (int fb = 0; fb < 5; ++fb) {
-        const int64_t m = cur[c][fb];
-        if (!m) continue;
-        tot += m;
-        const int r = c / w, col = c % w;
-        for (int a = 0; a < 4; ++a) {
-          const bool ok = a == 0 ? r > 0 : a == 1 ? col > 0 : a == 2 ? col < w - 1 : r < w - 1;
-          if (!ok || a == fb) continue;
-          const int n = c + (a == 0 ? -w : a == 1 ? -1 : a == 2 ? 1 : w);
-          nxt[n][3 - a] += m;
-        }
-      }
-    out[d] = (int32_t)std::min<int64_t>(tot, INT32_MAX);
-    memcpy(cur, nxt, sizeof cur);
-  }
+// `blank` of the 15-puzzle board (the exact size of each split-tree level).
+void level_sizes(int blank, int depth, int32_t* out) {
+  for (int d = 0; d <= depth; ++d) out[d] = g_ws.h_walks.v[1][blank][d];
 }
-
-void level_sizes(int blank, int depth, int32_t* out) { level_sizes_w(4, blank, depth, out); }
 
 int ensure_device() {
   int dev = 0;
@@ -156,12 +140,10 @@ int ensure_device() {
     return BPIDA_ENOMEM;
   if (hipEventCreate(&g_ws.ev0) != hipSuccess || hipEventCreate(&g_ws.ev1) != hipSuccess)
     return BPIDA_EDEVICE;
-  memset(g_ws.h_walks, 0, sizeof g_ws.h_walks);
-  for (int w = 3; w <= 5; ++w)
-    for (int c = 0; c < w * w; ++c) level_sizes_w(w, c, kMaxDepth, g_ws.h_walks[w - 3][c]);
-  if (g_ws.walks.ensure(sizeof g_ws.h_walks) != hipSuccess) return BPIDA_ENOMEM;
-  if (hipMemcpy(g_ws.walks.p, g_ws.h_walks, sizeof g_ws.h_walks, hipMemcpyHostToDevice) != hipSuccess)
+  if (walk_table_device(&g_ws.d_walks) != hipSuccess) {
+    (void)hipGetLastError();
     return BPIDA_EDEVICE;
+  }
   return BPIDA_OK;
 }
 
@@ -200,7 +182,8 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
   HIPCHK(launch_fill_outputs(d_len, d_nodes, n, st));
   if (n == 0) return BPIDA_OK;
   const int D = depth_for(O);
-  const int cap = cap_for(O, 16);
+  const int pnpl = (int)O.plain_nodes_per_round;
+  const int cap = cap_for(O, pnpl);
   const int spill_cap = (int)O.spill_capacity;
 
   // a1: ingest
@@ -234,7 +217,7 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
   HIPCHK(hipMemcpyAsync(W.tree_off.p, off.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st));
   HIPCHK(launch_zero_i32(W.err.as<int32_t>(), 1, st));
   HIPCHK(launch_split4(W.inst.as<Inst>(), n, D, W.tree_off.as<int64_t>(), 0,
-                       W.walks.as<int32_t>() + kWalkStride,
+                       W.d_walks + kWalkStride,
                        W.tree.as<Node>(), W.hist.as<uint32_t>(), W.goal_g.as<int32_t>(),
                        W.err.as<int32_t>(), nullptr, nullptr, st));
   int32_t split_err = 0;
@@ -243,7 +226,7 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
   if (split_err) return BPIDA_EINTERNAL;
 
   // a4..a9: persistent search grid and its scratch
-  int per_cu = search4_max_blocks_per_cu(cap);
+  int per_cu = search4_max_blocks_per_cu(cap, pnpl);
   if (per_cu <= 0) return BPIDA_EINVAL;
   int64_t max_grid = (int64_t)per_cu * W.num_cu;
   if (O.max_workgroups > 0) max_grid = std::min<int64_t>(max_grid, O.max_workgroups);
@@ -292,7 +275,7 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
           HIPCHK(launch_zero_i32(stop, 1, st));
         }
         HIPCHK(hipEventRecord(W.ev0, st));
-        HIPCHK(launch_search4(cap, grid, roots, nroots, L, W.cursor.as<int32_t>(),
+        HIPCHK(launch_search4(cap, pnpl, grid, roots, nroots, L, W.cursor.as<int32_t>(),
                               W.spill_t.as<uint64_t>(), W.spill_m.as<uint16_t>(), spill_cap,
                               W.part.as<Partial>(), stop, load, st));
         HIPCHK(hipEventRecord(W.ev1, st));
@@ -375,9 +358,9 @@ void tree_size(const Workspace& W, int w, int D, int64_t* stride, int64_t* max_r
   *max_roots = 0;
   for (int c = 0; c < w * w; ++c) {
     int64_t tot = 0;
-    for (int d = 0; d <= D; ++d) tot += W.h_walks[w - 3][c][d];
+    for (int d = 0; d <= D; ++d) tot += W.h_walks.v[w - 3][c][d];
     *stride = std::max(*stride, tot);
-    *max_roots = std::max<int64_t>(*max_roots, W.h_walks[w - 3][c][D]);
+    *max_roots = std::max<int64_t>(*max_roots, W.h_walks.v[w - 3][c][D]);
   }
 }
 
@@ -394,10 +377,173 @@ bool ring_fits(int w, int cap, int npl) {
   return cap / 2 >= 512;
 }
 
-int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
-                    int32_t* d_status, hipStream_t st, const Options& O, bool timed,
-                    int64_t* grid_out, int width = 4, const int32_t* h_widths = nullptr) {
+// Sizes of one batched solve.  Every buffer depends on n, the widths and D
+// only, and no value travels back to the host before the persistent launch:
+// the whole solve is one stream-ordered sequence of kernels.
+struct BatchPlan {
+  int n = 0, width = 4, D = 0, npl = 64, cap = 1024, sc = 64, wpg = 1;
+  bool any5 = false;
+  int64_t tree_nodes = 0, stride = 0, seed_chunks = 0, grid = 0;
+  uint64_t qcap = 64;       // queue slots (a power of two)
+  uint64_t qwant = 64;      // the default queue size (queue_capacity option, or sized from the batch)
+  std::vector<int64_t> toff, boff;  // mixed widths: split-tree and byte offsets per instance
+};
+
+// Device buffers of one batched solve.
+struct BatchBufs {
+  InstW* winst = nullptr;
+  NodeW* treew = nullptr;
+  uint32_t* hist = nullptr;
+  int32_t* goal_g = nullptr;
+  int32_t* err = nullptr;
+  int64_t* root_off = nullptr;
+  int32_t* nroots = nullptr;
+  QueueCtl* qctl = nullptr;
+  SlotCtl* qseq = nullptr;
+  QChunk* qslots = nullptr;
+  uint64_t* qhi = nullptr;  // 5x5 high words (any5 only)
+  InstState* istate = nullptr;
+  int32_t* widths = nullptr;    // mixed widths only
+  int64_t* byte_off = nullptr;  // mixed widths only
+  int64_t* tree_offw = nullptr; // mixed widths only
+};
+
+int plan_batched(int n, int width, const int32_t* h_widths, const Options& O, int num_cu,
+                 BatchPlan* P) {
+  const Workspace& W = g_ws;
+  P->n = n;
+  P->width = width;
+  P->D = depth_for(O);
+  P->npl = (int)O.nodes_per_round;
+  P->cap = cap_for(O, P->npl);
+  P->wpg = (int)(O.wg_size / 64);
+  const int per_cu = batch4_max_blocks_per_cu(P->cap, P->npl, P->wpg);
+  if (per_cu <= 0) return BPIDA_EINVAL;  // unsupported capacity for this round width
+  P->any5 = width == 5;
+  P->tree_nodes = P->seed_chunks = P->stride = 0;
+  if (!h_widths) {
+    int64_t mr = 0;
+    tree_size(W, width, P->D, &P->stride, &mr);
+    if (!ring_fits(width, P->cap, P->npl)) return BPIDA_EINVAL;
+    P->tree_nodes = P->stride * n;
+    P->seed_chunks = (int64_t)n * ((mr + kQChunk - 1) / kQChunk);
+  } else {
+    P->toff.assign((size_t)n, 0);
+    P->boff.assign((size_t)n, 0);
+    int64_t bytes = 0;
+    for (int i = 0; i < n; ++i) {
+      const int w = h_widths[i];
+      if (w < 3 || w > 5 || !ring_fits(w, P->cap, P->npl)) return BPIDA_EINVAL;
+      P->any5 = P->any5 || w == 5;
+      int64_t sw = 0, mr = 0;
+      tree_size(W, w, P->D, &sw, &mr);
+      P->toff[i] = P->tree_nodes;
+      P->boff[i] = bytes;
+      P->tree_nodes += sw;
+      bytes += (int64_t)w * w;
+      P->seed_chunks += (mr + kQChunk - 1) / kQChunk;
+    }
+  }
+  P->grid = (int64_t)per_cu * num_cu;
+  if (O.max_workgroups > 0) P->grid = std::min<int64_t>(P->grid, O.max_workgroups);
+  // Default queue size: the seeds plus, per wave, room for the chunks its
+  // stack overflows into.  Smaller stacks spill more (64-node rounds on
+  // a 512-entry stack spill ~10x more than on 1024), and a 5x5 subtree's
+  // stack runs deeper on a stack of half as many entries (measured peaks:
+  // about 6 chunks per workgroup for 4x4 batches on 1024 entries, 36 for
+  // 5x5).  Smaller seed chunks were measured not to help (the grid fills
+  // through donation within the first rounds), so 64 is the default.
+  P->sc = (int)O.seed_chunk;
+  P->seed_chunks *= kQChunk / P->sc;
+  const int64_t per_wg = P->any5 ? 64 : std::min<int64_t>(64, std::max<int64_t>(16, 32768 / P->cap));
+  const uint64_t want = O.queue_capacity > 0 ? (uint64_t)O.queue_capacity
+                                              : (uint64_t)(P->seed_chunks + P->grid * P->wpg * per_wg + 1024);
+  uint64_t q = 64;
+  while (q < want) q <<= 1;
+  P->qcap = P->qwant = q;
+  return BPIDA_OK;
+}
+
+// Lays the buffers of plan P out from byte address `base` (256-byte aligned
+// pieces) and returns the bytes used; base = 0 only measures.
+size_t carve_batched(uintptr_t base, const BatchPlan& P, BatchBufs* B) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> uintptr_t {
+    const uintptr_t p = base + off;
+    off += (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    return p;
+  };
+  const size_t n = (size_t)P.n;
+  B->winst = (InstW*)take(sizeof(InstW) * n);
+  B->treew = (NodeW*)take(sizeof(NodeW) * (size_t)P.tree_nodes);
+  B->hist = (uint32_t*)take(sizeof(uint32_t) * kHistBins * n);
+  B->goal_g = (int32_t*)take(sizeof(int32_t) * n);
+  B->err = (int32_t*)take(sizeof(int32_t));
+  B->root_off = (int64_t*)take(sizeof(int64_t) * n);
+  B->nroots = (int32_t*)take(sizeof(int32_t) * n);
+  B->qctl = (QueueCtl*)take(sizeof(QueueCtl));
+  B->qseq = (SlotCtl*)take(sizeof(SlotCtl) * P.qcap);
+  B->qslots = (QChunk*)take(sizeof(QChunk) * P.qcap);
+  B->qhi = P.any5 ? (uint64_t*)take(sizeof(uint64_t) * kQChunk * P.qcap) : nullptr;
+  B->istate = (InstState*)take(sizeof(InstState) * n);
+  if (!P.toff.empty()) {
+    B->widths = (int32_t*)take(sizeof(int32_t) * n);
+    B->byte_off = (int64_t*)take(sizeof(int64_t) * n);
+    B->tree_offw = (int64_t*)take(sizeof(int64_t) * n);
+  }
+  return off;
+}
+
+// The buffers of plan P from the library's grow-only workspace.
+int alloc_batched(const BatchPlan& P, BatchBufs* B) {
   Workspace& W = g_ws;
+  const size_t n = (size_t)P.n;
+  if (W.winst.ensure(sizeof(InstW) * n) != hipSuccess ||
+      W.treew.ensure(sizeof(NodeW) * (size_t)P.tree_nodes) != hipSuccess ||
+      W.hist.ensure(sizeof(uint32_t) * kHistBins * n) != hipSuccess ||
+      W.goal_g.ensure(sizeof(int32_t) * n) != hipSuccess || W.err.ensure(sizeof(int32_t)) != hipSuccess ||
+      W.root_off.ensure(sizeof(int64_t) * n) != hipSuccess ||
+      W.nroots.ensure(sizeof(int32_t) * n) != hipSuccess ||
+      W.qctl.ensure(sizeof(QueueCtl)) != hipSuccess ||
+      W.qseq.ensure(sizeof(SlotCtl) * P.qcap) != hipSuccess ||
+      W.qslots.ensure(sizeof(QChunk) * P.qcap) != hipSuccess ||
+      (P.any5 && W.qhi.ensure(sizeof(uint64_t) * kQChunk * P.qcap) != hipSuccess) ||
+      W.istate.ensure(sizeof(InstState) * n) != hipSuccess)
+    return g_no_alloc ? BPIDA_EINVAL : BPIDA_ENOMEM;
+  if (!P.toff.empty() &&
+      (W.widths.ensure(sizeof(int32_t) * n) != hipSuccess ||
+       W.byte_off.ensure(sizeof(int64_t) * n) != hipSuccess ||
+       W.tree_offw.ensure(sizeof(int64_t) * n) != hipSuccess))
+    return g_no_alloc ? BPIDA_EINVAL : BPIDA_ENOMEM;
+  B->winst = W.winst.as<InstW>();
+  B->treew = W.treew.as<NodeW>();
+  B->hist = W.hist.as<uint32_t>();
+  B->goal_g = W.goal_g.as<int32_t>();
+  B->err = W.err.as<int32_t>();
+  B->root_off = W.root_off.as<int64_t>();
+  B->nroots = W.nroots.as<int32_t>();
+  B->qctl = W.qctl.as<QueueCtl>();
+  B->qseq = W.qseq.as<SlotCtl>();
+  B->qslots = W.qslots.as<QChunk>();
+  B->qhi = P.any5 ? W.qhi.as<uint64_t>() : nullptr;
+  B->istate = W.istate.as<InstState>();
+  if (!P.toff.empty()) {
+    B->widths = W.widths.as<int32_t>();
+    B->byte_off = W.byte_off.as<int64_t>();
+    B->tree_offw = W.tree_offw.as<int64_t>();
+  }
+  return BPIDA_OK;
+}
+
+// Enqueues the whole batched solve of plan P on `st` into buffers B;
+// per-instance status (1 solved, < 0 bpida_status) lands in d_status.  No
+// host synchronisation and no copy to the host except the mixed-width
+// tables: the sequence can be recorded into a HIP graph.  `walks` is the
+// device walk-count table.
+int enqueue_batched_into(const uint8_t* d_states, int32_t* d_len, uint64_t* d_nodes,
+                         int32_t* d_status, hipStream_t st, const Options& O, const BatchPlan& P,
+                         const BatchBufs& B, const int32_t* walks, const int32_t* h_widths,
+                         hipEvent_t ev0, hipEvent_t ev1, int wall_khz) {
   hipError_t e;
 #define HIPCHK(x)              \
   do {                         \
@@ -407,117 +553,70 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
       return map_err(e);       \
     }                          \
   } while (0)
-
+  const int n = P.n;
   HIPCHK(launch_fill_outputs(d_len, d_nodes, n, st));
   if (n == 0) return BPIDA_OK;
-  const int D = depth_for(O);
-  const int npl = (int)O.nodes_per_round;
-  const int cap = cap_for(O, npl);
-  const int per_cu = batch4_max_blocks_per_cu(cap, npl);
-  if (per_cu <= 0) return BPIDA_EINVAL;  // unsupported capacity for this round width
-
-  // Every buffer size below depends on n, the widths and D only, and no
-  // value travels back to the host before the persistent launch: the whole
-  // solve is one stream-ordered sequence of kernels.
-  int64_t tree_nodes = 0, seed_chunks = 0, stride = 0;
-  bool any5 = width == 5;
-  if (!h_widths) {
-    int64_t mr = 0;
-    tree_size(W, width, D, &stride, &mr);
-    if (!ring_fits(width, cap, npl)) return BPIDA_EINVAL;
-    tree_nodes = stride * n;
-    seed_chunks = (int64_t)n * ((mr + kQChunk - 1) / kQChunk);
-  } else {
-    std::vector<int64_t> toff((size_t)n), boff((size_t)n);
-    int64_t bytes = 0;
-    for (int i = 0; i < n; ++i) {
-      const int w = h_widths[i];
-      if (w < 3 || w > 5 || !ring_fits(w, cap, npl)) return BPIDA_EINVAL;
-      any5 = any5 || w == 5;
-      int64_t sw = 0, mr = 0;
-      tree_size(W, w, D, &sw, &mr);
-      toff[i] = tree_nodes;
-      boff[i] = bytes;
-      tree_nodes += sw;
-      bytes += (int64_t)w * w;
-      seed_chunks += (mr + kQChunk - 1) / kQChunk;
-    }
-    HIPCHK(W.widths.ensure(sizeof(int32_t) * (size_t)n));
-    HIPCHK(W.byte_off.ensure(sizeof(int64_t) * (size_t)n));
-    HIPCHK(W.tree_offw.ensure(sizeof(int64_t) * (size_t)n));
-    HIPCHK(hipMemcpyAsync(W.widths.p, h_widths, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(W.byte_off.p, boff.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(W.tree_offw.p, toff.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st));
+  if (h_widths) {
+    HIPCHK(hipMemcpyAsync(B.widths, h_widths, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B.byte_off, P.boff.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B.tree_offw, P.toff.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st));
   }
-  HIPCHK(W.winst.ensure(sizeof(InstW) * (size_t)n));
-  HIPCHK(W.treew.ensure(sizeof(NodeW) * (size_t)tree_nodes));
-  HIPCHK(W.hist.ensure(sizeof(uint32_t) * kHistBins * (size_t)n));
-  HIPCHK(W.goal_g.ensure(sizeof(int32_t) * (size_t)n));
-  HIPCHK(W.err.ensure(sizeof(int32_t)));
-  HIPCHK(W.root_off.ensure(sizeof(int64_t) * (size_t)n));
-  HIPCHK(W.nroots.ensure(sizeof(int32_t) * (size_t)n));
-  HIPCHK(launch_ingestw(d_states, h_widths ? W.byte_off.as<int64_t>() : nullptr,
-                        h_widths ? W.widths.as<int32_t>() : nullptr, width, n, W.winst.as<InstW>(), st));
-  HIPCHK(launch_zero_i32(W.err.as<int32_t>(), 1, st));
-  HIPCHK(launch_splitw(W.winst.as<InstW>(), n, D, h_widths ? W.tree_offw.as<int64_t>() : nullptr,
-                       stride, W.walks.as<int32_t>(), W.treew.as<NodeW>(), W.hist.as<uint32_t>(),
-                       W.goal_g.as<int32_t>(), W.err.as<int32_t>(), W.root_off.as<int64_t>(),
-                       W.nroots.as<int32_t>(), st));
-
-  int64_t grid = (int64_t)per_cu * W.num_cu;
-  if (O.max_workgroups > 0) grid = std::min<int64_t>(grid, O.max_workgroups);
-  uint64_t qcap = 64;
-  // Default size: the seeds plus, per workgroup, room for the chunks its
-  // ring overflows into.  Smaller rings spill more (64-node rounds on a
-  // 512-entry ring spill ~10x more than on 1024), and a 5x5 subtree's stack
-  // runs deeper on a ring of half as many entries (measured peaks: about 6
-  // chunks per workgroup for 4x4 batches on 1024 entries, 36 for 5x5).
-  // Smaller seed chunks were measured not to help (the grid fills through
-  // donation within the first rounds), so 64 is the default.
-  const int sc = (int)O.seed_chunk;
-  seed_chunks *= kQChunk / sc;
-  const int64_t per_wg = any5 ? 64 : std::min<int64_t>(64, std::max<int64_t>(16, 32768 / cap));
-  const uint64_t want = O.queue_capacity > 0 ? (uint64_t)O.queue_capacity
-                                              : (uint64_t)(seed_chunks + grid * per_wg + 1024);
-  while (qcap < want) qcap <<= 1;
-  W.qcap = qcap;
-  HIPCHK(W.qctl.ensure(sizeof(QueueCtl)));
-  HIPCHK(W.qseq.ensure(sizeof(uint64_t) * qcap));
-  HIPCHK(W.qslots.ensure(sizeof(QChunk) * qcap));
-  HIPCHK(W.istate.ensure(sizeof(InstState) * (size_t)n));
-  HIPCHK(launch_zero_words(W.qctl.p, sizeof(QueueCtl), st));
+  HIPCHK(launch_ingestw(d_states, h_widths ? B.byte_off : nullptr, h_widths ? B.widths : nullptr,
+                        P.width, n, B.winst, st));
+  HIPCHK(launch_zero_i32(B.err, 1, st));
+  HIPCHK(launch_splitw(B.winst, n, P.D, h_widths ? B.tree_offw : nullptr, P.stride, walks, B.treew,
+                       B.hist, B.goal_g, B.err, B.root_off, B.nroots, st));
+  HIPCHK(launch_zero_words(B.qctl, sizeof(QueueCtl), st));
 
   BatchArgs A;
-  A.q = W.qctl.as<QueueCtl>();
-  A.seq = W.qseq.as<uint64_t>();
-  A.slots = W.qslots.as<QChunk>();
-  A.qmask = qcap - 1;
-  A.is = W.istate.as<InstState>();
-  A.tree = W.treew.as<NodeW>();
-  A.hist = W.hist.as<uint32_t>();
-  A.goal_g = W.goal_g.as<int32_t>();
+  memset(&A, 0, sizeof A);
+  A.q = B.qctl;
+  A.seq = B.qseq;
+  A.slots = B.qslots;
+  A.hi = B.qhi;
+  A.qmask = P.qcap - 1;
+  A.is = B.istate;
+  A.tree = B.treew;
+  A.hist = B.hist;
+  A.goal_g = B.goal_g;
   A.out_len = d_len;
   A.out_nodes = d_nodes;
   A.n = n;
   A.server = 0;
-  memset(&A.srv, 0, sizeof A.srv);
   A.max_limit = (int)(O.max_threshold >= 0 ? std::min<int64_t>(O.max_threshold, kMaxLimit) : kMaxLimit);
-  A.idle_ticks = (uint64_t)O.watchdog_ms * (uint64_t)W.wall_khz;
-  A.budget_ticks = (uint64_t)O.budget_ms * (uint64_t)W.wall_khz;
+  A.idle_ticks = (uint64_t)O.watchdog_ms * (uint64_t)wall_khz;
+  A.budget_ticks = (uint64_t)O.budget_ms * (uint64_t)wall_khz;
   A.donate_mask = (uint32_t)O.donate_every - 1u;
   A.donate_min = (int32_t)O.donate_min;
   A.donate_window = 2 * (int32_t)O.queue_chunk;
   A.first_solution = (int32_t)O.first_solution;
   A.start_limit = (int32_t)O.start_threshold;
-  A.seed_chunk = sc;
-  HIPCHK(launch_batch_setup(A, W.winst.as<InstW>(), W.root_off.as<int64_t>(), W.nroots.as<int32_t>(), st));
-  if (timed) HIPCHK(hipEventRecord(W.ev0, st));
-  HIPCHK(launch_batch4(cap, npl, (int)grid, A, st));
-  if (timed) HIPCHK(hipEventRecord(W.ev1, st));
-  HIPCHK(launch_batch_status(A.is, n, A.q, W.err.as<int32_t>(), d_status, st));
-  *grid_out = grid;
+  A.seed_chunk = P.sc;
+  A.push_spin = (int32_t)O.push_spin;
+  HIPCHK(launch_batch_setup(A, B.winst, B.root_off, B.nroots, st));
+  if (ev0) HIPCHK(hipEventRecord(ev0, st));
+  HIPCHK(launch_batch4(P.cap, P.npl, P.wpg, (int)P.grid, A, st));
+  if (ev1) HIPCHK(hipEventRecord(ev1, st));
+  HIPCHK(launch_batch_status(A.is, n, A.q, B.err, d_status, st));
   return BPIDA_OK;
 #undef HIPCHK
+}
+
+int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
+                    int32_t* d_status, hipStream_t st, const Options& O, bool timed,
+                    int64_t* grid_out, int width = 4, const int32_t* h_widths = nullptr) {
+  Workspace& W = g_ws;
+  if (n == 0) return map_err(launch_fill_outputs(d_len, d_nodes, n, st));
+  BatchPlan P;
+  int rc = plan_batched(n, width, h_widths, O, W.num_cu, &P);
+  if (rc != BPIDA_OK) return rc;
+  BatchBufs B;
+  rc = alloc_batched(P, &B);
+  if (rc != BPIDA_OK) return rc;
+  W.qcap = P.qcap;
+  *grid_out = P.grid;
+  return enqueue_batched_into(d_states, d_len, d_nodes, d_status, st, O, P, B, W.d_walks, h_widths,
+                              timed ? W.ev0 : nullptr, timed ? W.ev1 : nullptr, W.wall_khz);
 }
 
 // The batched driver: enqueue, then wait and read the status back.
@@ -747,11 +846,12 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     const int D = depth_for(O);
     const int npl = (int)O.nodes_per_round;
     const int cap = cap_for(O, npl);
-    const int per_cu = batch4_max_blocks_per_cu(cap, npl);
+    const int wpg = (int)(O.wg_size / 64);
+    const int per_cu = batch4_max_blocks_per_cu(cap, npl, wpg);
     if (per_cu <= 0 || !ring_fits(4, cap, npl)) return BPIDA_EINVAL;
     int64_t grid = (int64_t)per_cu * W.num_cu;
     if (O.max_workgroups > 0) grid = std::min<int64_t>(grid, O.max_workgroups);
-    if (grid < 2) return BPIDA_EINVAL;  // one admitter plus at least one searcher
+    if (grid * wpg < 2) return BPIDA_EINVAL;  // one admitter plus at least one searcher
     int64_t stride = 0, max_roots = 0;
     tree_size(W, 4, D, &stride, &max_roots);
     const int64_t S = max_inflight;
@@ -759,12 +859,15 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     while (ring < (uint64_t)ring_capacity) ring <<= 1;
     const int sc_srv = (int)O.seed_chunk;
     uint64_t qcap = 64;
+    // as a batch: the seeds of every slot plus, per workgroup, room for the
+    // chunks its stack overflows into (smaller stacks spill more)
+    const int64_t per_wg = std::min<int64_t>(64, std::max<int64_t>(16, 32768 / cap));
     const uint64_t want = O.queue_capacity > 0
                               ? (uint64_t)O.queue_capacity
-                              : (uint64_t)(S * ((max_roots + sc_srv - 1) / sc_srv) + grid * 32 + 1024);
+                              : (uint64_t)(S * ((max_roots + sc_srv - 1) / sc_srv) + grid * wpg * per_wg + 1024);
     while (qcap < want) qcap <<= 1;
     free_server_host(V);
-    if (V.qctl.ensure(sizeof(QueueCtl)) != hipSuccess || V.qseq.ensure(sizeof(uint64_t) * qcap) != hipSuccess ||
+    if (V.qctl.ensure(sizeof(QueueCtl)) != hipSuccess || V.qseq.ensure(sizeof(SlotCtl) * qcap) != hipSuccess ||
         V.qslots.ensure(sizeof(QChunk) * qcap) != hipSuccess ||
         V.istate.ensure(sizeof(InstState) * S) != hipSuccess ||
         V.tree.ensure(sizeof(NodeW) * S * stride) != hipSuccess ||
@@ -802,7 +905,7 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     BatchArgs A;
     memset(&A, 0, sizeof A);
     A.q = V.qctl.as<QueueCtl>();
-    A.seq = V.qseq.as<uint64_t>();
+    A.seq = V.qseq.as<SlotCtl>();
     A.slots = V.qslots.as<QChunk>();
     A.qmask = qcap - 1;
     A.is = V.istate.as<InstState>();
@@ -821,6 +924,7 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     A.first_solution = (int32_t)O.first_solution;
     A.start_limit = (int32_t)O.start_threshold;
     A.seed_chunk = sc_srv;
+    A.push_spin = (int32_t)O.push_spin;
     A.server = 1;
     A.srv.host = V.host;
     A.srv.req = V.req;
@@ -831,12 +935,12 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     A.srv.stride = stride;
     A.srv.busy = V.busy.as<int32_t>();
     A.srv.ticket = V.ticket.as<uint64_t>();
-    A.srv.walks = W.walks.as<int32_t>() + kWalkStride;
+    A.srv.walks = W.d_walks + kWalkStride;
     A.srv.admitter = V.admitter.as<int32_t>();
     A.srv.in_flight = V.inflight.as<int32_t>();
     if (launch_zero_words(V.qctl.p, sizeof(QueueCtl), V.stream) != hipSuccess ||
         launch_server_setup(A, V.stream) != hipSuccess ||
-        launch_batch4(cap, npl, (int)grid, A, V.stream) != hipSuccess) {
+        launch_batch4(cap, npl, wpg, (int)grid, A, V.stream) != hipSuccess) {
       (void)hipGetLastError();
       return BPIDA_EDEVICE;
     }
@@ -1002,6 +1106,15 @@ extern "C" int bpida_set_option(const char* key, int64_t value) {
   } else if (k == "queue_chunk") {
     if (value != 16 && value != 32 && value != 64) return BPIDA_EINVAL;
     g_opt.queue_chunk = value;
+  } else if (k == "wg_size") {
+    if (value != 64 && value != 128 && value != 256) return BPIDA_EINVAL;
+    g_opt.wg_size = value;
+  } else if (k == "plain_nodes_per_round") {
+    if (value != 16 && value != 64) return BPIDA_EINVAL;
+    g_opt.plain_nodes_per_round = value;
+  } else if (k == "push_spin") {
+    if (value < 1 || value > (int64_t(1) << 24)) return BPIDA_EINVAL;
+    g_opt.push_spin = value;
   } else if (k == "donate_min") {
     if (value != -1 && (value < 2 || value > 2048)) return BPIDA_EINVAL;
     g_opt.donate_min = value;
@@ -1032,6 +1145,9 @@ extern "C" int64_t bpida_get_option(const char* key) {
   if (k == "static_lb") return g_opt.static_lb;
   if (k == "start_threshold") return g_opt.start_threshold;
   if (k == "seed_chunk") return g_opt.seed_chunk;
+  if (k == "push_spin") return g_opt.push_spin;
+  if (k == "plain_nodes_per_round") return g_opt.plain_nodes_per_round;
+  if (k == "wg_size") return g_opt.wg_size;
   return INT64_MIN;
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <stdint.h>
 
 #include <algorithm>
@@ -127,6 +128,43 @@ constexpr int kMaxDepth = 16;  // deepest root split
 constexpr int kWalkCells = 25;  // walk-count table: [width - 3][cell][length]
 constexpr int kWalkStride = kWalkCells * (kMaxDepth + 1);
 
+// Exact split-tree level sizes: v[w - 3][c][d] = number of blank walks of
+// length d from cell c of a width-w board that never undo their previous
+// move (every level of the parent-pruned tree, no duplicate elimination).
+struct WalkTable {
+  int32_t v[3][kWalkCells][kMaxDepth + 1];
+};
+
+constexpr WalkTable make_walk_table() {
+  WalkTable t{};
+  for (int w = 3; w <= 5; ++w)
+    for (int blank = 0; blank < w * w; ++blank) {
+      // cur[c][f]: walks ending at cell c whose next move may not be f (4: any)
+      int64_t cur[kWalkCells][5] = {};
+      cur[blank][4] = 1;
+      for (int d = 0; d <= kMaxDepth; ++d) {
+        int64_t tot = 0, nxt[kWalkCells][5] = {};
+        for (int c = 0; c < w * w; ++c)
+          for (int fb = 0; fb < 5; ++fb) {
+            const int64_t m = cur[c][fb];
+            if (!m) continue;
+            tot += m;
+            const int r = c / w, col = c % w;
+            for (int a = 0; a < 4; ++a) {
+              const bool ok = a == 0 ? r > 0 : a == 1 ? col > 0 : a == 2 ? col < w - 1 : r < w - 1;
+              if (!ok || a == fb) continue;
+              const int n = c + (a == 0 ? -w : a == 1 ? -1 : a == 2 ? 1 : w);
+              nxt[n][3 - a] += m;
+            }
+          }
+        t.v[w - 3][blank][d] = (int32_t)(tot < INT32_MAX ? tot : INT32_MAX);
+        for (int c = 0; c < kWalkCells; ++c)
+          for (int fb = 0; fb < 5; ++fb) cur[c][fb] = nxt[c][fb];
+      }
+    }
+  return t;
+}
+
 // ---------------------------------------------------------------------------
 // Batched persistent search (bpida_batch.hip).
 // ---------------------------------------------------------------------------
@@ -138,12 +176,23 @@ constexpr int kQChunk = 64;  // stack entries per queue chunk
 // BPIDA_ENOMEM and its workgroups stop early.
 constexpr int32_t kErrFatal = 1 | 2 | 16;
 
+// Bits 64..127 of a 5x5 chunk's states live in a parallel array (BatchArgs::hi),
+// so a 3x3 or 4x4 chunk moves 6 cache lines, not 10.
 struct alignas(128) QChunk {
   uint64_t tiles[kQChunk];  // packed states, bits 0..63
-  uint64_t hi[kQChunk];     // bits 64..127 (5x5 only)
   uint16_t meta[kQChunk];
   int32_t inst;
   int32_t count;
+  int32_t wide;  // 1: a 5x5 chunk, whose high words are in BatchArgs::hi
+};
+
+// Per-slot control words of the queue ring, for the next ticket t to use the
+// slot: seq == 4t free for producer t, 4t + 1 claimed by it, 4t + 2 holds
+// ticket t's chunk; abandoned = 1 + the largest ticket whose producer gave up
+// on this slot (ring full for its whole bounded wait), 0 if none.
+struct SlotCtl {
+  uint64_t seq;
+  uint64_t abandoned;
 };
 
 // Per-instance search state.
@@ -159,6 +208,8 @@ struct InstState {
   int32_t nroots;
   int32_t width;        // board width 3, 4 or 5
   int32_t stop;         // first-solution mode: a goal was expanded, drop the rest
+  int32_t lost;         // some of this instance's work was dropped (queue full):
+                        // its counts are void (server mode answers BPIDA_ENOMEM)
 };
 
 // Queue control block and run counters.  The fields that many workgroups
@@ -217,8 +268,9 @@ struct ServerArgs {
 
 struct BatchArgs {
   QueueCtl* q;
-  uint64_t* seq;       // per slot sequence number
+  SlotCtl* seq;        // per slot sequence number and abandoned-ticket mark
   QChunk* slots;
+  uint64_t* hi;        // per slot 64 words: bits 64..127 of a 5x5 chunk (null: no 5x5 instance)
   uint64_t qmask;      // capacity - 1 (capacity a power of two)
   InstState* is;
   const NodeW* tree;
@@ -236,11 +288,15 @@ struct BatchArgs {
   int32_t first_solution; // nonzero: the final limit stops at its first goal
   int32_t start_limit;    // first f-limit to search (< 0: h0)
   int32_t seed_chunk;     // roots per seeded chunk (8..64)
+  int32_t push_spin;     // polls of a full slot before a push gives its ticket up
   int32_t server;        // nonzero: continuous-batching server (srv below)
   ServerArgs srv;
 };
 
 hipError_t launch_server_setup(const BatchArgs& A, hipStream_t s);
+// Device address of the walk-count table (a constant-initialised device
+// variable: no allocation).
+hipError_t walk_table_device(const int32_t** out);
 
 hipError_t launch_batch_setup(const BatchArgs& A, const InstW* d_inst, const int64_t* d_root_off,
                               const int32_t* d_nroots, hipStream_t s);
@@ -250,10 +306,10 @@ hipError_t launch_splitw(const InstW* d_inst, int n, int depth, const int64_t* d
                          int64_t stride, const int32_t* d_walks, NodeW* d_tree, uint32_t* d_hist,
                          int32_t* d_goal_g, int32_t* d_err, int64_t* d_root_off, int32_t* d_nroots,
                          hipStream_t s);
-hipError_t launch_batch4(int lds_cap, int npl, int grid, const BatchArgs& A, hipStream_t s);
+hipError_t launch_batch4(int lds_cap, int npl, int wpg, int grid, const BatchArgs& A, hipStream_t s);
 hipError_t launch_batch_status(const InstState* d_is, int n, const QueueCtl* d_q,
                                const int32_t* d_split_err, int32_t* d_status, hipStream_t s);
-int batch4_max_blocks_per_cu(int lds_cap, int npl);
+int batch4_max_blocks_per_cu(int lds_cap, int npl, int wpg);
 
 // Kernel launchers (bpida_kernels.hip).
 hipError_t launch_ingest4(const uint8_t* d_states, int n, Inst* d_inst, hipStream_t s);
@@ -261,7 +317,7 @@ hipError_t launch_split4(const Inst* d_inst, int n, int depth, const int64_t* d_
                          int64_t stride, const int32_t* d_walks, Node* d_tree, uint32_t* d_hist,
                          int32_t* d_goal_g, int32_t* d_err, int64_t* d_root_off, int32_t* d_nroots,
                          hipStream_t s);
-hipError_t launch_search4(int lds_cap, int grid, const Node* d_roots, int nroots, int limit,
+hipError_t launch_search4(int lds_cap, int npl, int grid, const Node* d_roots, int nroots, int limit,
                           int32_t* d_cursor, uint64_t* d_spill_tiles, uint16_t* d_spill_meta,
                           int spill_cap, Partial* d_part, int32_t* d_stop, uint32_t* d_load,
                           hipStream_t s);
@@ -281,6 +337,6 @@ hipError_t launch_fill_outputs(int32_t* d_len, uint64_t* d_nodes, int n, hipStre
 hipError_t launch_set_len(int32_t* d_len_i, int32_t value, hipStream_t s);
 hipError_t launch_zero_i32(int32_t* d_p, int n, hipStream_t s);
 hipError_t launch_zero_words(void* d_p, size_t bytes, hipStream_t s);
-int search4_max_blocks_per_cu(int lds_cap);
+int search4_max_blocks_per_cu(int lds_cap, int npl);
 
 }  // namespace bpida

@@ -10,10 +10,13 @@
 //            node l/4 with move l%4 (the threadID mod #actions map), and the
 //            surviving children are pushed with a ballot + mbcnt prefix
 //            (atomicPut; one wave makes it a single linearizable step)
+//   search64 the same launch with 64-node rounds: one popped node per lane,
+//            its four moves unrolled (the batched kernel's round)
 //   reduce   per-limit node total, next limit and goal flag (the min/stat
 //            combine that Alg. 1 performs across its parallel blocks)
 #include <limits.h>
 
+#include "bpida_board.h"
 #include "bpida_internal.h"
 #include "bpida_round.h"
 
@@ -304,6 +307,131 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
   }
 }
 
+// search64: as search4 (persistent grid, roots through the cursor, HBM spill
+// stack per workgroup, first-solution stop flag, per-root round counts for
+// the static load balancing), with 64-node rounds on a linear LDS stack
+// [0, top).  Entry CAP - 1 takes the children a round drops (its stores are
+// branch-free), so the stack proper ends at CAP - 1.  The oldest 64 entries
+// go to the spill stack when the largest round (192 new entries: a start
+// node has four children) might not fit; when fewer than 64 entries remain,
+// the last spilled chunk comes back below them.
+template <int CAP>
+__global__ __launch_bounds__(64) void search64_kernel(const Node* __restrict__ roots, int nroots,
+                                                      int limit, int32_t* __restrict__ cursor,
+                                                      uint64_t* __restrict__ spill_tiles,
+                                                      uint16_t* __restrict__ spill_meta,
+                                                      int spill_cap, Partial* __restrict__ part,
+                                                      int32_t* __restrict__ stop,
+                                                      uint32_t* __restrict__ load) {
+  static_assert((CAP & (CAP - 1)) == 0 && CAP >= 512, "stack size for 64-node rounds");
+  __shared__ __attribute__((aligned(16))) uint64_t st[CAP];
+  __shared__ uint16_t sm[CAP];
+  constexpr uint32_t kCap = CAP - 1;
+  constexpr uint32_t kGrow = 3 * 64;
+
+  const int lane = threadIdx.x;
+  uint64_t* sp_t = spill_tiles + (size_t)blockIdx.x * spill_cap;
+  uint16_t* sp_m = spill_meta + (size_t)blockIdx.x * spill_cap;
+
+  uint64_t expanded = 0, rounds = 0, spilled = 0;
+  int goals = 0;
+  int fmin = INT_MAX;
+  int err = 0;
+  int spill_hw = 0;
+
+  bool stopped = false;
+  for (;;) {
+    if (stop && wave_bcast(lane == 0 ? __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0))
+      break;
+    int r = 0;
+    if (lane == 0) r = atomicAdd(cursor, 1);
+    r = wave_bcast(r);
+    if (r >= nroots) break;
+    const Node R = roots[r];
+    if ((int)R.f > limit) {
+      fmin = min(fmin, (int)R.f);
+      continue;
+    }
+    if (lane == 0) {
+      st[0] = R.tiles;
+      sm[0] = (uint16_t)((R.meta & 0xFFu) | ((uint32_t)(limit - (int)R.f) << 8));
+    }
+    WAVE_SYNC();
+    const uint64_t rounds0 = rounds;
+    uint32_t top = 1;
+    int sp = 0;
+    for (;;) {
+      if (top < 64u && sp > 0) {
+        // the last spilled chunk comes back below the remaining entries
+        uint64_t t = 0;
+        uint16_t m = 0;
+        if ((uint32_t)lane < top) {
+          t = st[lane];
+          m = sm[lane];
+        }
+        WAVE_SYNC();
+        if ((uint32_t)lane < top) {
+          st[64 + lane] = t;
+          sm[64 + lane] = m;
+        }
+        sp -= 64;
+        st[lane] = sp_t[sp + lane];
+        sm[lane] = sp_m[sp + lane];
+        top += 64u;
+        WAVE_SYNC();
+      }
+      if (top == 0) break;
+      if (top + kGrow > kCap) {
+        if (sp + 64 > spill_cap) {
+          err = 1;  // entries are dropped; the host reports BPIDA_ENOMEM
+        } else {
+          sp_t[sp + lane] = st[lane];
+          sp_m[sp + lane] = sm[lane];
+          sp += 64;
+          spilled += 64;
+          spill_hw = max(spill_hw, sp);
+        }
+        WAVE_SYNC();
+        move_down(st, sm, 0u, 64u, top - 64u);
+        top -= 64u;
+      }
+      const int kp = (int)min(top, 64u);
+      top = bp_round64w<4, CAP, true>(st, sm, top, kp, goals);
+      expanded += (uint64_t)kp;
+      rounds += 1;
+      if (stop) {
+        if (goals > 0) {
+          if (lane == 0) __hip_atomic_store(stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          stopped = true;
+          break;
+        }
+        if ((rounds & 63u) == 0 &&
+            wave_bcast(lane == 0 ? __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0)) {
+          stopped = true;
+          break;
+        }
+      }
+    }
+    if (load && lane == 0) load[r] = (uint32_t)min<uint64_t>(rounds - rounds0, 0xFFFFFFFFull);
+    if (stopped) break;
+  }
+  // 64-node rounds do not track pruned f: every pruned child has f = limit + 2
+  // (all slacks are even), and a limit below the optimum always prunes one
+  if (expanded > 0) fmin = min(fmin, limit + 2);
+  fmin = wave_min(fmin);
+  if (lane == 0) {
+    Partial P;
+    P.nodes = expanded;
+    P.rounds = rounds;
+    P.spilled = spilled;
+    P.fmin = fmin;
+    P.goals = goals;
+    P.err = err;
+    P.spill_hw = spill_hw;
+    part[blockIdx.x] = P;
+  }
+}
+
 template <int CAP>
 static hipError_t launch_search4_t(int grid, const Node* d_roots, int nroots, int limit,
                                    int32_t* d_cursor, uint64_t* d_st, uint16_t* d_sm, int spill_cap,
@@ -313,11 +441,33 @@ static hipError_t launch_search4_t(int grid, const Node* d_roots, int nroots, in
   return hipGetLastError();
 }
 
-hipError_t launch_search4(int lds_cap, int grid, const Node* d_roots, int nroots, int limit,
+template <int CAP>
+static hipError_t launch_search64_t(int grid, const Node* d_roots, int nroots, int limit,
+                                    int32_t* d_cursor, uint64_t* d_st, uint16_t* d_sm, int spill_cap,
+                                    Partial* d_part, int32_t* d_stop, uint32_t* d_load, hipStream_t s) {
+  hipLaunchKernelGGL(search64_kernel<CAP>, dim3(grid), dim3(64), 0, s, d_roots, nroots, limit,
+                     d_cursor, d_st, d_sm, spill_cap, d_part, d_stop, d_load);
+  return hipGetLastError();
+}
+
+hipError_t launch_search4(int lds_cap, int npl, int grid, const Node* d_roots, int nroots, int limit,
                           int32_t* d_cursor, uint64_t* d_spill_tiles, uint16_t* d_spill_meta,
                           int spill_cap, Partial* d_part, int32_t* d_stop, uint32_t* d_load,
                           hipStream_t s) {
   if (grid <= 0) return hipSuccess;
+  if (npl == 64) {
+    switch (lds_cap) {
+#define CASE(C)                                                                                 \
+  case C:                                                                                       \
+    return launch_search64_t<C>(grid, d_roots, nroots, limit, d_cursor, d_spill_tiles,          \
+                                d_spill_meta, spill_cap, d_part, d_stop, d_load, s);
+      CASE(512) CASE(1024) CASE(2048)
+#undef CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  if (npl != 16) return hipErrorInvalidValue;
   switch (lds_cap) {
 #define CASE(C)                                                                                 \
   case C:                                                                                       \
@@ -330,9 +480,19 @@ hipError_t launch_search4(int lds_cap, int grid, const Node* d_roots, int nroots
   }
 }
 
-int search4_max_blocks_per_cu(int lds_cap) {
+int search4_max_blocks_per_cu(int lds_cap, int npl) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
+  if (npl == 64) {
+    switch (lds_cap) {
+      case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, search64_kernel<512>, 64, 0); break;
+      case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, search64_kernel<1024>, 64, 0); break;
+      case 2048: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, search64_kernel<2048>, 64, 0); break;
+      default: break;
+    }
+    return e == hipSuccess ? nb : 0;
+  }
+  if (npl != 16) return 0;
   switch (lds_cap) {
     case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, search4_kernel<128>, 64, 0); break;
     case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, search4_kernel<256>, 64, 0); break;

@@ -18,6 +18,20 @@ namespace bpida {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
   } while (0)
 
+// Lane of this thread within its wave64 (workgroups of the batched kernel
+// may hold several independent waves).
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+// Orders this wave's LDS and global accesses across its lanes, like a
+// workgroup barrier in a one-wave workgroup, without waiting for the other
+// waves of the workgroup (which run independently).
+#define WAVE_SYNC_MEM()                                    \
+  do {                                                     \
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup"); \
+    __builtin_amdgcn_wave_barrier();                       \
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup"); \
+  } while (0)
+
 // Per-lane constants of the lane -> (popped entry, move) map: lane l expands
 // entry l/4 with move l%4 (the threadID mod #actions rule of Alg. 1).
 struct LaneMap {
@@ -89,6 +103,24 @@ __device__ __forceinline__ uint32_t bp_round(uint64_t* st, uint16_t* sm, uint32_
   }
   WAVE_SYNC();
   return base + (uint32_t)__popcll(km);
+}
+
+// Moves LDS stack entries [src, src + n) down to [dst, dst + n), dst < src,
+// 64 at a time in ascending order: every entry is read before anything is
+// written over it.
+template <typename S>
+__device__ __forceinline__ void move_down(S* st, uint16_t* sm, uint32_t dst, uint32_t src, uint32_t n) {
+  const uint32_t lane = (uint32_t)lane_id();
+  for (uint32_t i = 0; i < n; i += 64u) {
+    const uint32_t k = i + lane;
+    if (k < n) {
+      const S t = st[src + k];
+      const uint16_t m = sm[src + k];
+      st[dst + k] = t;
+      sm[dst + k] = m;
+    }
+  }
+  WAVE_SYNC();
 }
 
 __device__ __forceinline__ int wave_max(int v) {

@@ -63,6 +63,13 @@ def test_argument_errors_before_device_work(B):
                                           ctypes.c_void_p(8), None) == B.EINVAL
     assert B.lib.bpida_solve_mixed_device(ctypes.c_void_p(8), wp, 0, ctypes.c_void_p(8),
                                           ctypes.c_void_p(8), None) == B.OK
+    for fn in (B.lib.bpida_solve_device_async,):
+        v = ctypes.c_void_p(8)
+        assert fn(None, 1, 4, v, v, v, None) == B.EINVAL
+        assert fn(v, 1, 4, v, v, None, None) == B.EINVAL
+        assert fn(v, -1, 4, v, v, v, None) == B.EINVAL
+        assert fn(v, 1, 6, v, v, v, None) == B.EINVAL
+        assert fn(v, 0, 4, v, v, v, None) == B.OK
     assert (ln == 0).all() and (nd == 0).all()  # outputs untouched
 
 
@@ -75,7 +82,8 @@ def test_options_roundtrip_and_validation(B):
                  ("queue_capacity", -1), ("watchdog_ms", 0),
                  ("spill_capacity", 65), ("max_threshold", -2), ("donate_every", 48),
                  ("donate_every", 2), ("donate_min", 0), ("donate_min", 4096), ("queue_chunk", 48), ("start_threshold", -2), ("seed_chunk", 12), ("seed_chunk", -1),
-                 ("static_lb", 2), ("first_solution", 2), ("no_such_key", 1)):
+                 ("static_lb", 2), ("first_solution", 2), ("wg_size", 96), ("wg_size", 512),
+                 ("plain_nodes_per_round", 32), ("push_spin", 0), ("no_such_key", 1)):
         with pytest.raises(B.BpidaError):
             B.set_option(k, v)
     assert B.get_option("no_such_key") == -(2 ** 63)
@@ -96,3 +104,18 @@ def test_mixed_binding_rejects_non_square_states(B):
     import numpy as np
     with pytest.raises(ValueError):
         B.solve_mixed_raw([np.arange(9, dtype=np.uint8), np.arange(10, dtype=np.uint8)])
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """The binding loads torch before the library, so the process maps one
+    HIP runtime (torch's) even when the binding is imported first."""
+    import subprocess
+    import sys
+    code = ("from paper_1705_02843_amd import bpida\n"
+            "import torch\n"
+            "m = open('/proc/self/maps').read().splitlines()\n"
+            "print(len(set(l.split()[-1] for l in m if 'libamdhip64' in l)))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

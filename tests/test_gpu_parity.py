@@ -33,10 +33,14 @@ def B():
 OPTION_KEYS = ("mode", "frontier_depth", "lds_stack_capacity", "spill_capacity",
                "max_workgroups", "max_threshold", "queue_capacity", "watchdog_ms",
                "nodes_per_round", "budget_ms", "first_solution", "static_lb", "start_threshold",
-               "seed_chunk")
+               "seed_chunk", "plain_nodes_per_round", "push_spin", "wg_size")
 # plain: one launch per instance and limit, 16-node rounds (Alg. 1's map);
-# batched: persistent launch, 64-node rounds; batched16: persistent, 16-node
-MODES = {"plain": {"mode": 0}, "batched": {"mode": 1, "nodes_per_round": 64},
+# plain64: the same with 64-node rounds; batched: persistent launch, 64-node
+# rounds; batched16: persistent, 16-node rounds (tracks pruned f, so every
+# limit advance checks f_next = L + 2 on the device)
+MODES = {"plain": {"mode": 0, "plain_nodes_per_round": 16},
+         "plain64": {"mode": 0, "plain_nodes_per_round": 64},
+         "batched": {"mode": 1, "nodes_per_round": 64},
          "batched16": {"mode": 1, "nodes_per_round": 16}}
 
 
@@ -118,8 +122,9 @@ def test_split_depths_agree(opts, depth, mode):
     assert_parity(ln, nodes, want_len, want_nodes, "D=%d" % depth)
 
 
-CAPS = [("plain", 128), ("plain", 1024), ("batched16", 128), ("batched16", 256),
-        ("batched16", 2048), ("batched", 512), ("batched", 1024), ("batched", 2048)]
+CAPS = [("plain", 128), ("plain", 1024), ("plain64", 512), ("plain64", 2048),
+        ("batched16", 128), ("batched16", 256), ("batched16", 2048), ("batched", 512),
+        ("batched", 1024), ("batched", 2048)]
 
 
 @pytest.mark.parametrize("mode,cap", CAPS)
@@ -135,7 +140,7 @@ def test_lds_capacity_and_spill_agree(opts, cap, mode):
     rc, ln, nodes = B.solve_raw(states)
     assert rc == B.OK, B.strerror(rc)
     assert_parity(ln, nodes, want_len, want_nodes, "cap=%d" % cap)
-    if cap == 128 or (mode == "batched" and cap == 512):
+    if cap == 128 or (mode in ("batched", "plain64") and cap == 512):
         assert B.last_stats()["spilled"] > 0  # the spill path was exercised
 
 
@@ -306,15 +311,20 @@ def test_lost_work_fails_fast(opts):
     assert dt < 5.0, dt
 
 
-def test_c3_4096_batched_exact_where_stored_and_valid_everywhere(opts):
+@pytest.mark.parametrize("mode,wg", [("batched", 64), ("batched16", 64), ("batched", 128),
+                                     ("batched", 256)])
+def test_c3_4096_batched_exact_where_stored_and_valid_everywhere(opts, mode, wg):
     """The 4096-state uneven workload in one persistent launch (the grid is
     smaller than the batch): exact against the stored oracle results, and
-    every instance consistent with its walk and its heuristic."""
+    every instance consistent with its walk and its heuristic, for every
+    workgroup size.  With 16-node rounds every pruned child's f is tracked
+    and each limit advance checks f_next = L + 2 on the device."""
     B = opts
     from paper_1705_02843_amd import instances as I
-    _say("case: c3_uneven, 4096 states, batched (64-node rounds)")
+    _say("case: c3_uneven, 4096 states, %s, wg_size %d" % (mode, wg))
     states, walk = I.c3_uneven()
-    set_mode(B, "batched")
+    set_mode(B, mode)
+    B.set_option("wg_size", wg)
     rc, ln, nodes = B.solve_raw(states)
     assert rc == B.OK, B.strerror(rc)
     name = "c3_uneven" if os.path.exists(os.path.join(GOLDEN, "c3_uneven.json")) else \
@@ -368,7 +378,30 @@ def test_plain_static_lb_small_split_depth(opts):
     assert B.last_stats()["lb_roots_added"] > 0
 
 
-@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_plain64_static_load_balancing_exact(opts):
+    """Plain BPIDA* with 64-node rounds and the static load balancing: the
+    per-root round counts it re-splits by come from the other kernel."""
+    B = opts
+    _say("case: plain64, static_lb=1, first 30 of c2_md30_38")
+    set_mode(B, "plain64")
+    B.set_option("static_lb", 1)
+    states, length, nodes = load_golden("c2_md30_38")
+    rc, ln, got = B.solve_raw(states[:30])
+    assert rc == B.OK, B.strerror(rc)
+    assert_parity(ln, got, length[:30], nodes[:30], "plain64 lb")
+    assert B.last_stats()["lb_roots_added"] > 0
+
+
+def test_plain64_rejects_small_stacks(opts):
+    B = opts
+    set_mode(B, "plain64")
+    B.set_option("lds_stack_capacity", 256)
+    states, _, _ = load_golden("c1_walk40")
+    rc, _, _ = B.solve_raw(states[:2])
+    assert rc == B.EINVAL
+
+
+@pytest.mark.parametrize("mode", ["plain", "plain64", "batched"])
 def test_start_threshold_at_the_optimum(opts, mode):
     """Starting at the optimal length (or one below it: rounded up to h0's
     parity) runs only the final limit: its count is the stored one, the
@@ -389,6 +422,32 @@ def test_start_threshold_at_the_optimum(opts, mode):
                 assert not got[0, k:].any()
     finally:
         B.set_option("start_threshold", -1)
+
+
+@pytest.mark.parametrize("wg", [128, 256])
+def test_workgroup_size_does_not_change_results(opts, wg):
+    """Two or four independent waves per workgroup, each with its own stack:
+    every count equal to the stored oracle results, also with a grid of a
+    few workgroups (donation between waves of one workgroup and across)."""
+    B = opts
+    set_mode(B, "batched")
+    B.set_option("wg_size", wg)
+    for name, k, maxwg in (("c1_walk40", 64, 0), ("c2_md30_38", 30, 0), ("c2_md30_38", 12, 3)):
+        _say("case: batched, wg_size=%d, %s first %d, max_workgroups=%d" % (wg, name, k, maxwg))
+        B.set_option("max_workgroups", maxwg)
+        states, length, nodes = load_golden(name)
+        rc, ln, got = B.solve_raw(states[:k])
+        assert rc == B.OK, B.strerror(rc)
+        assert_parity(ln, got, length[:k], nodes[:k], "%s wg=%d" % (name, wg))
+
+
+def test_workgroup_size_needs_64_node_rounds(opts):
+    B = opts
+    set_mode(B, "batched16")
+    B.set_option("wg_size", 128)
+    states, _, _ = load_golden("c1_walk40")
+    rc, _, _ = B.solve_raw(states[:2])
+    assert rc == B.EINVAL
 
 
 @pytest.mark.parametrize("sc", [8, 16])

@@ -128,3 +128,53 @@ def test_full_ring_reports_eagain_and_recovers(B):
     for t, (k, r) in res.items():
         assert r is not None and r[2] == 1 and r[0] == l1[k] and (r[1] == n1[k]).all()
     assert r2[0] == l1[5] and (r2[1] == n1[5]).all()
+
+
+def test_queue_overflow_answers_enomem_never_wrong_counts(B):
+    print("case: server with a 64-slot queue, a 1-poll push wait and one searching "
+          "workgroup, 64 + 12 golden states", flush=True)
+    s1, l1, n1 = load_golden("c1_walk40")
+    s2, l2, n2 = load_golden("c2_md30_38")
+    # the 12 smallest of c2 (at most 4.1e6 nodes each): one workgroup searches them
+    pick = [39, 77, 26, 96, 17, 44, 30, 84, 35, 36, 70, 66]
+    states = np.concatenate([s1, s2[pick]])
+    want_len = np.concatenate([l1, l2[pick]])
+    want_nodes = np.concatenate([n1, n2[pick]])
+    saved = {k: B.get_option(k) for k in ("queue_capacity", "push_spin", "max_workgroups")}
+    B.set_option("queue_capacity", 64)
+    B.set_option("push_spin", 1)
+    B.set_option("max_workgroups", 2)  # the admitter and one searcher
+    got, pending = {}, {}
+    try:
+        with B.Server(max_inflight=64, ring_capacity=256) as srv:
+            for k in range(len(states)):
+                t = srv.submit(states[k])
+                assert t is not None
+                pending[t] = k
+            drain(srv, pending, got, time.time() + 60)
+            rc = srv.stop()
+    finally:
+        for k, v in saved.items():
+            B.set_option(k, v)
+    assert not pending and len(got) == len(states)
+    lost = 0
+    for k in range(len(states)):
+        ln, nodes, status = got[k]
+        if status == B.ENOMEM:
+            lost += 1
+            assert ln == -1, k
+            continue
+        assert status == 1, (k, status)
+        assert ln == want_len[k] and (nodes == want_nodes[k]).all(), k
+    print("answers lost to the full queue: %d of %d; stop rc %d" % (lost, len(states), rc),
+          flush=True)
+    assert lost > 0 and rc == B.ENOMEM
+    # a fresh server with the default queue answers every request exactly
+    with B.Server(max_inflight=16, ring_capacity=64) as srv:
+        t = srv.submit(s1[7])
+        r = None
+        deadline = time.time() + 30
+        while r is None and time.time() < deadline:
+            r = srv.poll(t)
+        assert srv.stop() == B.OK
+    assert r is not None and r[2] == 1 and r[0] == l1[7] and (r[1] == n1[7]).all()

@@ -159,6 +159,29 @@ def test_c4_mixed_one_launch_exact_and_same_as_alone(B):
         off += k
 
 
+def test_c4_4x4_part_with_16_node_rounds_exact(B):
+    """The 2048 4x4 states of the mixed workload with 16-node rounds, which
+    track every pruned child's f (the device checks f_next = L + 2 at each
+    limit advance): exact against the stored oracle results."""
+    from paper_1705_02843_amd import instances as I
+    g = _golden("c4_mixed_w4")
+    if g is None:
+        pytest.skip("no stored results for the 4x4 part")
+    print("case: c4 4x4 part, 2048 states, batched 16-node rounds", flush=True)
+    s = I.c4_mixed()[4][0]
+    old = B.get_option("nodes_per_round")
+    B.set_option("nodes_per_round", 16)
+    try:
+        rc, ln, nodes = B.solve_raw(s, 4)
+    finally:
+        B.set_option("nodes_per_round", old)
+    assert rc == B.OK, B.strerror(rc)
+    for i, r in enumerate(g["instances"]):
+        m = len(r["nodes"])
+        assert ln[i] == r["length"], i
+        assert list(nodes[i, :m]) == r["nodes"] and not nodes[i, m:].any(), i
+
+
 def test_mixed_batch_with_bad_states(B):
     """Invalid and unsolvable boards of every width inside one mixed batch:
     each gets its own status (-1 length, zero counts), the first failing code
