@@ -138,6 +138,31 @@ int bpida_solve_device_async(const uint8_t *d_states, int32_t n_instances, int32
                              void *hip_stream);
 
 /*
+ * As bpida_solve_device_async, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The call allocates nothing: every buffer the solve
+ * needs besides the caller's inputs and outputs (ingested states, split
+ * tree, interior histograms, work queue, per-instance search state) is
+ * carved from one fixed device array of BPIDA_NOALLOC_SCRATCH_BYTES per
+ * GPU, which the library holds until the process ends.  Buffers, options,
+ * ordering and d_status as in bpida_solve_device_async (batched mode, one
+ * board width).  The work queue sized from the batch is shrunk to fit the
+ * array when needed (not below the seeds plus 1024 chunks; a queue_capacity
+ * option is kept as set); a queue that then overflows marks every instance
+ * BPIDA_ENOMEM in d_status.  Returns BPIDA_ENOMEM, before any device work,
+ * if the batch's buffers do not fit (e.g. 4096 4x4 instances fit at the
+ * default split depth 6, about 1500 at depth 8).  Every call on one GPU
+ * shares that GPU's array: two calls whose enqueued work overlaps in time
+ * (on two streams with no ordering between them) race and give wrong
+ * results; order them on one stream.  The array keeps the last call's
+ * contents; each call initialises everything it reads.
+ */
+#define BPIDA_NOALLOC_SCRATCH_BYTES (128u << 20)
+int bpida_solve_device_noalloc(const uint8_t *d_states, int32_t n_instances, int32_t width,
+                               int32_t *d_len, uint64_t *d_nodes, int32_t *d_status,
+                               void *hip_stream);
+
+/*
  * Continuous-batching server (one per process).  bpida_server_start launches
  * a persistent search kernel on `hip_stream` (NULL: a stream of the
  * library's own) and returns at once; the kernel keeps running, admitting

@@ -12,13 +12,14 @@ import os
 import numpy as np
 
 MAX_THRESHOLDS = 64
+NOALLOC_SCRATCH_BYTES = 128 << 20  # BPIDA_NOALLOC_SCRATCH_BYTES
 OK, EINVAL, EUNSOLVABLE, ELIMIT, ENOMEM, EDEVICE, EINTERNAL, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbpida.so")
 
 EXPORTS = ("bpida_solve", "bpida_solve_mixed", "bpida_solve_mixed_device", "bpida_solve_device",
-           "bpida_solve_device_async", "bpida_set_option",
+           "bpida_solve_device_async", "bpida_solve_device_noalloc", "bpida_set_option",
            "bpida_get_option", "bpida_last_stats", "bpida_strerror", "bpida_server_start",
            "bpida_server_submit", "bpida_server_poll", "bpida_server_stop")
 
@@ -60,6 +61,8 @@ def _load() -> ctypes.CDLL:
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p]
     lib.bpida_solve_device_async.restype = ctypes.c_int
+    lib.bpida_solve_device_noalloc.argtypes = lib.bpida_solve_device_async.argtypes
+    lib.bpida_solve_device_noalloc.restype = ctypes.c_int
     lib.bpida_server_start.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_void_p]
     lib.bpida_server_start.restype = ctypes.c_int
@@ -208,6 +211,26 @@ def solve_device_async(d_states, d_len, d_nodes, d_status, width: int = 4, strea
                                             ctypes.c_void_p(d_nodes.data_ptr()),
                                             ctypes.c_void_p(d_status.data_ptr()),
                                             ctypes.c_void_p(s.cuda_stream)))
+
+
+def solve_device_noalloc(d_states, d_len, d_nodes, d_status, width: int = 4, stream=None) -> int:
+    """As ``solve_device_async`` through the entry point that allocates no
+    device memory (its buffers come from a fixed array inside the library)."""
+    import torch  # device buffers and streams only
+
+    n = int(d_states.shape[0])
+    assert d_states.is_cuda and d_states.dtype == torch.uint8 and d_states.is_contiguous()
+    assert d_states.numel() == n * width * width
+    assert d_len.is_cuda and d_len.dtype == torch.int32 and d_len.numel() >= n
+    assert d_status.is_cuda and d_status.dtype == torch.int32 and d_status.numel() >= n
+    assert d_nodes.is_cuda and d_nodes.dtype in (torch.int64, torch.uint64)
+    assert d_nodes.is_contiguous() and d_nodes.numel() >= n * MAX_THRESHOLDS
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(lib.bpida_solve_device_noalloc(ctypes.c_void_p(d_states.data_ptr()), n, width,
+                                              ctypes.c_void_p(d_len.data_ptr()),
+                                              ctypes.c_void_p(d_nodes.data_ptr()),
+                                              ctypes.c_void_p(d_status.data_ptr()),
+                                              ctypes.c_void_p(s.cuda_stream)))
 
 
 class Server:

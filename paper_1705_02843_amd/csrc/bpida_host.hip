@@ -1171,3 +1171,102 @@ extern "C" const char* bpida_strerror(int code) {
     default: return "unknown status";
   }
 }
+
+// ---------------------------------------------------------------------------
+// Batched solve that allocates nothing: every buffer is carved from one
+// fixed device array per GPU, `scratch`.  Host code never uses the array's
+// name as a device address: its address on each device comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+// ---------------------------------------------------------------------------
+namespace bpida {
+namespace {
+
+static __device__ __align__(256) uint8_t scratch[BPIDA_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxNoAllocDevices = 64;
+
+struct NoAllocDevice {
+  bool init = false;
+  int rc = BPIDA_OK;
+  uint8_t* ptr = nullptr;         // device address of `scratch` on this device
+  const int32_t* walks = nullptr; // device address of the walk-count table
+  int num_cu = 0;
+  int wall_khz = 100000;
+};
+
+NoAllocDevice g_noalloc[kMaxNoAllocDevices];
+
+// Once per device, with the device current: its properties and the device
+// addresses of the scratch array and the walk table.
+int noalloc_init(int dev) {
+  NoAllocDevice& D = g_noalloc[dev];
+  if (D.init) return D.rc;
+  D.init = true;
+  D.rc = BPIDA_EDEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return D.rc;
+  }
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return D.rc;
+  D.num_cu = prop.multiProcessorCount;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+    D.wall_khz = khz;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return D.rc;
+  }
+  D.ptr = static_cast<uint8_t*>(p);
+  if (walk_table_device(&D.walks) != hipSuccess || !D.walks) {
+    (void)hipGetLastError();
+    return D.rc;
+  }
+  D.rc = BPIDA_OK;
+  return D.rc;
+}
+
+}  // namespace
+}  // namespace bpida
+
+extern "C" int bpida_solve_device_noalloc(const uint8_t* d_states, int32_t n_instances, int32_t width,
+                                          int32_t* d_len, uint64_t* d_nodes, int32_t* d_status,
+                                          void* hip_stream) {
+  try {
+    if (!d_states || !d_len || !d_nodes || !d_status || n_instances < 0) return BPIDA_EINVAL;
+    if (check_opts(width) != BPIDA_OK) return BPIDA_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Options O = g_opt;
+    O.mode = kModeBatched;
+    if (n_instances == 0) return BPIDA_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxNoAllocDevices) {
+      (void)hipGetLastError();
+      return BPIDA_EDEVICE;
+    }
+    int rc = noalloc_init(dev);
+    if (rc != BPIDA_OK) return rc;
+    const NoAllocDevice& D = g_noalloc[dev];
+    BatchPlan P;
+    rc = plan_batched(n_instances, width, nullptr, O, D.num_cu, &P);
+    if (rc != BPIDA_OK) return rc;
+    // A queue sized from the batch may not fit: shrink it, never below the
+    // seeds plus 1024 chunks (a queue that then overflows while searching
+    // reports BPIDA_ENOMEM per instance); a queue_capacity option is kept.
+    BatchBufs B;
+    uint64_t qmin = 64;
+    while (qmin < (uint64_t)P.seed_chunks + 1024) qmin <<= 1;
+    while (O.queue_capacity == 0 && P.qcap > qmin &&
+           carve_batched(0, P, &B) > (size_t)BPIDA_NOALLOC_SCRATCH_BYTES)
+      P.qcap >>= 1;
+    if (carve_batched(0, P, &B) > (size_t)BPIDA_NOALLOC_SCRATCH_BYTES) return BPIDA_ENOMEM;
+    carve_batched((uintptr_t)D.ptr, P, &B);
+    return enqueue_batched_into(d_states, d_len, d_nodes, d_status, (hipStream_t)hip_stream, O, P, B,
+                                D.walks, nullptr, nullptr, nullptr, D.wall_khz);
+  } catch (const std::bad_alloc&) {
+    return BPIDA_ENOMEM;
+  } catch (...) {
+    return BPIDA_EINTERNAL;
+  }
+}

@@ -63,7 +63,7 @@ def test_argument_errors_before_device_work(B):
                                           ctypes.c_void_p(8), None) == B.EINVAL
     assert B.lib.bpida_solve_mixed_device(ctypes.c_void_p(8), wp, 0, ctypes.c_void_p(8),
                                           ctypes.c_void_p(8), None) == B.OK
-    for fn in (B.lib.bpida_solve_device_async,):
+    for fn in (B.lib.bpida_solve_device_async, B.lib.bpida_solve_device_noalloc):
         v = ctypes.c_void_p(8)
         assert fn(None, 1, 4, v, v, v, None) == B.EINVAL
         assert fn(v, 1, 4, v, v, None, None) == B.EINVAL
