@@ -29,7 +29,12 @@
  *   - "expanded" = every node the DFS visits, start and goal nodes included.
  *
  * Output per instance: the optimal length, the sequence of f-limits used and
- * the number of nodes expanded under each of them.
+ * the number of nodes expanded under each of them, and optionally one
+ * optimal path (Alg. 1's BPDFS returns the goal "and its parents"): the moves
+ * from the start to the first goal the DFS expands.  The final limit is the
+ * optimal length and every pruned subtree holds no goal within it, so the
+ * depth-first order U, L, R, D makes that path the lexicographically
+ * smallest optimal move sequence (unique, whichever final-limit mode runs).
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -37,6 +42,7 @@
 #include <string.h>
 
 #define ORACLE_MAX_ITERS 64
+#define ORACLE_MAX_PATH 256 /* moves per path (f-limits stay below 256) */
 #define ORACLE_MAX_WIDTH 5
 #define ORACLE_MAX_CELLS (ORACLE_MAX_WIDTH * ORACLE_MAX_WIDTH)
 
@@ -84,6 +90,9 @@ typedef struct {
   int first;        /* first-solution mode: stop at the first goal         */
   int hbad;         /* check mode found a mismatch                         */
   uint8_t s[ORACLE_MAX_CELLS];
+  uint8_t moves[ORACLE_MAX_PATH]; /* moves from the start to the current node */
+  uint8_t *path;    /* null, or where the first goal's moves are copied    */
+  int path_len;     /* moves copied to path (-1: none yet)                 */
 } search_t;
 
 /* Blank at `blank`, path cost g, heuristic h, `last` = move that produced
@@ -93,6 +102,11 @@ static void dfs(search_t *S, int blank, int g, int h, int last) {
   S->count++;
   if (S->check && md_full(w, S->s) != h) S->hbad = 1;
   if (h == 0 && is_goal(w, S->s)) {
+    if (!S->found && S->path && g <= ORACLE_MAX_PATH) {
+      /* the first goal of this iteration: its path is the current moves */
+      memcpy(S->path, S->moves, (size_t)g);
+      S->path_len = g;
+    }
     S->found = 1;
     if (S->first) return; /* first solution: the search ends here */
   }                       /* all solutions: continue */
@@ -115,6 +129,7 @@ static void dfs(search_t *S, int blank, int g, int h, int last) {
     }
     S->s[blank] = (uint8_t)t;
     S->s[n] = 0;
+    if (g < ORACLE_MAX_PATH) S->moves[g] = (uint8_t)a;
     dfs(S, n, g + 1, hc, a);
     S->s[n] = (uint8_t)t;
     S->s[blank] = 0;
@@ -152,12 +167,15 @@ int oracle_check_state(const uint8_t *s, int32_t w) {
 
 int32_t oracle_manhattan(const uint8_t *s, int32_t w) { return md_full(w, s); }
 
-/* Solve one instance.  limits[j], nodes[j] for j < *niter. */
+/* Solve one instance.  limits[j], nodes[j] for j < *niter; path (null, or
+ * ORACLE_MAX_PATH bytes): the moves of the first goal expanded, 0xFF after. */
 static int solve_one(const uint8_t *start, int w, int check, int first, int max_limit,
-                     int32_t *len, int32_t *limits, uint64_t *nodes, int32_t *niter) {
+                     int32_t *len, int32_t *limits, uint64_t *nodes, int32_t *niter,
+                     uint8_t *path) {
   *len = -1;
   *niter = 0;
   for (int j = 0; j < ORACLE_MAX_ITERS; ++j) { limits[j] = 0; nodes[j] = 0; }
+  if (path) memset(path, 0xFF, ORACLE_MAX_PATH);
   int rc = oracle_check_state(start, w);
   if (rc != ORACLE_OK) return rc;
   search_t S;
@@ -165,6 +183,8 @@ static int solve_one(const uint8_t *start, int w, int check, int first, int max_
   S.w = w;
   S.check = check;
   S.first = first;
+  S.path = path;
+  S.path_len = -1;
   memcpy(S.s, start, (size_t)(w * w));
   int blank = 0;
   while (start[blank] != 0) ++blank;
@@ -194,6 +214,7 @@ typedef struct {
   int n, w, check, first, max_limit;
   int32_t *len, *limits, *niter, *status;
   uint64_t *nodes;
+  uint8_t *paths; /* null, or n * ORACLE_MAX_PATH */
   int next; /* shared cursor, taken under the lock */
   pthread_mutex_t mu;
 } batch_t;
@@ -209,7 +230,8 @@ static void *worker(void *arg) {
     B->status[i] = solve_one(B->states + (size_t)i * nn, B->w, B->check, B->first, B->max_limit,
                              &B->len[i],
                              B->limits + (size_t)i * ORACLE_MAX_ITERS,
-                             B->nodes + (size_t)i * ORACLE_MAX_ITERS, &B->niter[i]);
+                             B->nodes + (size_t)i * ORACLE_MAX_ITERS, &B->niter[i],
+                             B->paths ? B->paths + (size_t)i * ORACLE_MAX_PATH : NULL);
   }
   return NULL;
 }
@@ -225,18 +247,21 @@ static void *worker(void *arg) {
  * check      nonzero: recompute h from scratch at every node
  * max_limit  stop with ORACLE_ELIMIT before an f-limit above this (< 0: none)
  * first      nonzero: the final iteration returns at its first goal
+ * out_path   host, n * 256 or null: the moves (U, L, R, D = 0..3) of the
+ *            first goal expanded, 0xFF past the length
  * Returns ORACLE_OK if every instance solved, else the first failing code.
  */
-int oracle_solve(const uint8_t *states, int32_t n, int32_t width, int32_t *out_len,
-                 int32_t *out_limits, uint64_t *out_nodes, int32_t *out_niter,
-                 int32_t *out_status, int32_t nthreads, int32_t check, int32_t max_limit,
-                 int32_t first) {
+int oracle_solve_paths(const uint8_t *states, int32_t n, int32_t width, int32_t *out_len,
+                       int32_t *out_limits, uint64_t *out_nodes, int32_t *out_niter,
+                       int32_t *out_status, int32_t nthreads, int32_t check, int32_t max_limit,
+                       int32_t first, uint8_t *out_path) {
   if (!states || !out_len || !out_limits || !out_nodes || !out_niter || !out_status || n < 0 ||
       width < 2 || width > ORACLE_MAX_WIDTH)
     return ORACLE_EINVAL;
   batch_t B;
   B.states = states; B.n = n; B.w = width; B.check = check; B.first = first;
   B.max_limit = max_limit;
+  B.paths = out_path;
   B.len = out_len; B.limits = out_limits; B.nodes = out_nodes; B.niter = out_niter;
   B.status = out_status; B.next = 0;
   pthread_mutex_init(&B.mu, NULL);
@@ -252,4 +277,12 @@ int oracle_solve(const uint8_t *states, int32_t n, int32_t width, int32_t *out_l
   for (int i = 0; i < n; ++i)
     if (out_status[i] != ORACLE_OK) return out_status[i];
   return ORACLE_OK;
+}
+
+int oracle_solve(const uint8_t *states, int32_t n, int32_t width, int32_t *out_len,
+                 int32_t *out_limits, uint64_t *out_nodes, int32_t *out_niter,
+                 int32_t *out_status, int32_t nthreads, int32_t check, int32_t max_limit,
+                 int32_t first) {
+  return oracle_solve_paths(states, n, width, out_len, out_limits, out_nodes, out_niter,
+                            out_status, nthreads, check, max_limit, first, NULL);
 }

@@ -19,6 +19,7 @@ from dataclasses import dataclass
 import numpy as np
 
 MAX_ITERS = 64
+MAX_PATH = 256
 OK, EINVAL, EUNSOLVABLE, ELIMIT, EHCHECK = 0, -1, -2, -3, -4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -50,6 +51,8 @@ def _load():
                                      p(ctypes.c_int32), p(ctypes.c_int32), ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         lib.oracle_solve.restype = ctypes.c_int32
+        lib.oracle_solve_paths.argtypes = lib.oracle_solve.argtypes + [p(ctypes.c_uint8)]
+        lib.oracle_solve_paths.restype = ctypes.c_int32
         lib.oracle_check_state.argtypes = [p(ctypes.c_uint8), ctypes.c_int32]
         lib.oracle_check_state.restype = ctypes.c_int32
         lib.oracle_manhattan.argtypes = [p(ctypes.c_uint8), ctypes.c_int32]
@@ -70,6 +73,7 @@ class OracleResult:
     nodes: np.ndarray    # uint64[n, 64]
     niter: np.ndarray    # int32[n]
     status: np.ndarray   # int32[n]
+    path: np.ndarray | None = None  # uint8[n, 256]: moves U, L, R, D = 0..3, 0xFF after
 
     @property
     def total_nodes(self) -> int:
@@ -77,9 +81,12 @@ class OracleResult:
 
 
 def solve(states, width: int, nthreads: int = 1, check: bool = False,
-          max_limit: int = -1, first_solution: bool = False) -> OracleResult:
+          max_limit: int = -1, first_solution: bool = False,
+          with_path: bool = False) -> OracleResult:
     """IDA* per instance (all optimal solutions in the final iteration, or
-    with ``first_solution`` stopping at its first goal, as Alg. 1 returns)."""
+    with ``first_solution`` stopping at its first goal, as Alg. 1 returns).
+    ``with_path``: also the moves to the first goal expanded (the
+    lexicographically smallest optimal move sequence)."""
     lib = _load()
     st = np.ascontiguousarray(np.asarray(states, dtype=np.uint8).reshape(-1, width * width))
     n = st.shape[0]
@@ -88,14 +95,16 @@ def solve(states, width: int, nthreads: int = 1, check: bool = False,
     nodes = np.zeros((n, MAX_ITERS), np.uint64)
     niter = np.zeros(n, np.int32)
     status = np.zeros(n, np.int32)
+    path = np.full((n, MAX_PATH), 0xFF, np.uint8) if with_path else None
     if n == 0:
-        return OracleResult(OK, length, limits, nodes, niter, status)
-    rc = lib.oracle_solve(_ptr(st, ctypes.c_uint8), n, width, _ptr(length, ctypes.c_int32),
-                          _ptr(limits, ctypes.c_int32), _ptr(nodes, ctypes.c_uint64),
-                          _ptr(niter, ctypes.c_int32), _ptr(status, ctypes.c_int32),
-                          int(nthreads), int(bool(check)), int(max_limit),
-                          int(bool(first_solution)))
-    return OracleResult(int(rc), length, limits, nodes, niter, status)
+        return OracleResult(OK, length, limits, nodes, niter, status, path)
+    rc = lib.oracle_solve_paths(_ptr(st, ctypes.c_uint8), n, width, _ptr(length, ctypes.c_int32),
+                                _ptr(limits, ctypes.c_int32), _ptr(nodes, ctypes.c_uint64),
+                                _ptr(niter, ctypes.c_int32), _ptr(status, ctypes.c_int32),
+                                int(nthreads), int(bool(check)), int(max_limit),
+                                int(bool(first_solution)),
+                                _ptr(path, ctypes.c_uint8) if with_path else None)
+    return OracleResult(int(rc), length, limits, nodes, niter, status, path)
 
 
 def check_state(state, width: int) -> int:

@@ -103,3 +103,35 @@ def random_state_at(w: int, moves: list[int]) -> tuple:
 
 def as_array(states) -> np.ndarray:
     return np.asarray(list(states), dtype=np.uint8)
+
+
+def first_shortest_moves(state: tuple, w: int, dist: dict) -> list:
+    """The lexicographically smallest shortest move sequence from ``state`` to
+    the goal, from exact distances: at each step the first move (U, L, R, D)
+    whose child is one step closer.  Every state on a shortest path from a
+    state at distance d is within distance d, so a bounded BFS suffices."""
+    out = []
+    s = state
+    d = dist[s]
+    while d > 0:
+        for a, c in neighbours(s, w):
+            if dist.get(c) == d - 1:
+                out.append(a)
+                s, d = c, d - 1
+                break
+        else:
+            raise ValueError("no step closer: distances are not exact")
+    return out
+
+
+def replay(state: tuple, w: int, moves) -> tuple:
+    """Apply blank moves to a state; raises on a move off the board."""
+    s = state
+    for a in moves:
+        for aa, c in neighbours(s, w):
+            if aa == int(a):
+                s = c
+                break
+        else:
+            raise ValueError("illegal move %d" % int(a))
+    return s

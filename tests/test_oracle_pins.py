@@ -145,6 +145,29 @@ def test_limits_rise_by_two_and_end_at_optimum(bfs3):
         assert r.limits[i, k - 1] == bfs3[s] == r.length[i]
 
 
+def test_3x3_paths_are_the_first_shortest_move_sequences(bfs3):
+    """The oracle's path (moves to the first goal its DFS expands) is, for
+    every 3x3 state, a shortest path whose first move is the first (U, L, R,
+    D order) that gets one step closer by BFS distance; on a sample the whole
+    path equals the lexicographically smallest shortest move sequence."""
+    states = list(bfs3.keys())
+    for first in (False, True):
+        r = oracle.solve(P.as_array(states), 3, nthreads=8, first_solution=first, with_path=True)
+        assert r.rc == 0
+        for i, s in enumerate(states):
+            d = bfs3[s]
+            p = r.path[i]
+            assert (p[d:] == 0xFF).all() and (p[:d] < 4).all()
+            if d:
+                for a, c in P.neighbours(s, 3):
+                    if bfs3[c] == d - 1:
+                        assert p[0] == a, s
+                        break
+            if i % 11 == 0:
+                assert list(p[:d]) == P.first_shortest_moves(s, 3, bfs3), s
+                assert P.replay(s, 3, p[:d]) == P.goal(3)
+
+
 # ---- 4x4 ------------------------------------------------------------------
 
 @pytest.fixture(scope="module")
@@ -165,6 +188,34 @@ def test_4x4_lengths_equal_bounded_bfs(bfs4):
     r = _solve(pick, 4)
     assert r.rc == 0
     np.testing.assert_array_equal(r.length, [bfs4[s] for s in pick])
+
+
+def test_4x4_paths_are_the_first_shortest_move_sequences(bfs4):
+    rng = np.random.default_rng(9)
+    by_depth = {}
+    for s, d in bfs4.items():
+        by_depth.setdefault(d, []).append(s)
+    pick = []
+    for d in sorted(by_depth):
+        lst = by_depth[d]
+        for i in rng.choice(len(lst), min(len(lst), 20), replace=False):
+            pick.append(lst[i])
+    r = oracle.solve(P.as_array(pick), 4, nthreads=8, with_path=True)
+    assert r.rc == 0
+    for i, s in enumerate(pick):
+        d = bfs4[s]
+        assert list(r.path[i, :d]) == P.first_shortest_moves(s, 4, bfs4), s
+        assert (r.path[i, d:] == 0xFF).all()
+
+
+def test_4x4_paths_replay_to_the_goal():
+    s, _ = I.c1_walk40(n=16)
+    r = oracle.solve(s, 4, nthreads=8, with_path=True)
+    assert r.rc == 0
+    for i in range(len(s)):
+        L = int(r.length[i])
+        end = P.replay(tuple(int(x) for x in s[i]), 4, r.path[i, :L])
+        assert end == P.goal(4) and (r.path[i, L:] == 0xFF).all()
 
 
 def test_4x4_counts_equal_layer_recurrence():
@@ -193,6 +244,20 @@ def test_4x4_walk_bounds_and_check_mode():
         assert list(r.limits[i, :k]) == [h0[i] + 2 * j for j in range(k)]
         # each f-limited iteration repeats (at least) all of the previous one
         assert all(r.nodes[i, j + 1] > r.nodes[i, j] for j in range(k - 1))
+
+
+def test_5x5_counts_equal_layer_recurrence():
+    """Per-limit counts of short 5x5 walks at every limit, against the
+    layered path-count recurrence (5 bits per tile on the GPU side)."""
+    rng = np.random.default_rng(25)
+    picks = [tuple(int(x) for x in I.random_walk(rng, 5, k)[0]) for k in (8, 12, 14)]
+    r = _solve(picks, 5)
+    assert r.rc == 0
+    for i, s in enumerate(picks):
+        assert r.niter[i] >= 1
+        for j in range(r.niter[i]):
+            L = int(r.limits[i, j])
+            assert int(r.nodes[i, j]) == P.layered_path_count(s, 5, L), (s, L)
 
 
 @pytest.mark.parametrize("w", [3, 5])
