@@ -84,6 +84,40 @@ enum bpida_status {
 int bpida_solve(const uint8_t *states, int32_t n_instances, int32_t width, int32_t *out_len,
                 uint64_t *out_nodes_per_threshold);
 
+/* Bytes per returned path: moves of the blank, U, L, R, D = 0..3, one per
+ * byte, 0xFF past the path's end. */
+#define BPIDA_MAX_PATH 256
+
+/*
+ * As bpida_solve (batched mode, one board width) plus one optimal path per
+ * instance: Alg. 1's BPDFS returns the goal "and its parents as a shortest
+ * path".  out_path: host, n_instances * BPIDA_MAX_PATH bytes; row i holds
+ * out_len[i] moves of the blank (U, L, R, D = 0..3) leading from state i to
+ * the goal, then 0xFF (all 0xFF for an instance that is invalid, unsolvable,
+ * capped, or already the goal).  The path is the lexicographically smallest
+ * optimal move sequence (U < L < R < D), so it is unique: the first goal a
+ * sequential depth-first search in that move order meets at the optimal
+ * limit.  It is rebuilt after the solve by exact-limit probes: per move, each
+ * legal child of the current state is searched at the single limit "moves
+ * left - 1" (first goal only), and the first child that reaches the goal is
+ * taken; the probes of all instances run in one batched launch per move.
+ * out_len and out_nodes_per_threshold are those of bpida_solve (all optimal
+ * solutions in the final limit unless the first_solution option is set).
+ * Return value as bpida_solve; BPIDA_EINTERNAL if some probe round found no
+ * child one step closer (never expected).  Synchronous.
+ */
+int bpida_solve_paths(const uint8_t *states, int32_t n_instances, int32_t width, int32_t *out_len,
+                      uint64_t *out_nodes_per_threshold, uint8_t *out_path);
+
+/*
+ * As bpida_solve_paths with every buffer in device memory of the current
+ * device (d_path: n * BPIDA_MAX_PATH bytes), ordered on `hip_stream`; returns
+ * after the results are in place (one host read of the lengths between the
+ * solve and the probes, and one at the end).
+ */
+int bpida_solve_paths_device(const uint8_t *d_states, int32_t n_instances, int32_t width,
+                             int32_t *d_len, uint64_t *d_nodes, uint8_t *d_path, void *hip_stream);
+
 /*
  * As bpida_solve for a batch that mixes board widths, always in batched mode
  * (one persistent launch for all of them).  widths: host, n int32 in 3..5.

@@ -12,13 +12,15 @@ import os
 import numpy as np
 
 MAX_THRESHOLDS = 64
+MAX_PATH = 256  # BPIDA_MAX_PATH
 NOALLOC_SCRATCH_BYTES = 128 << 20  # BPIDA_NOALLOC_SCRATCH_BYTES
 OK, EINVAL, EUNSOLVABLE, ELIMIT, ENOMEM, EDEVICE, EINTERNAL, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbpida.so")
 
-EXPORTS = ("bpida_solve", "bpida_solve_mixed", "bpida_solve_mixed_device", "bpida_solve_device",
+EXPORTS = ("bpida_solve", "bpida_solve_paths", "bpida_solve_paths_device", "bpida_solve_mixed",
+           "bpida_solve_mixed_device", "bpida_solve_device",
            "bpida_solve_device_async", "bpida_solve_device_noalloc", "bpida_set_option",
            "bpida_get_option", "bpida_last_stats", "bpida_strerror", "bpida_server_start",
            "bpida_server_submit", "bpida_server_poll", "bpida_server_stop")
@@ -48,6 +50,13 @@ def _load() -> ctypes.CDLL:
     lib.bpida_solve.argtypes = [P(ctypes.c_uint8), ctypes.c_int32, ctypes.c_int32,
                                 P(ctypes.c_int32), P(ctypes.c_uint64)]
     lib.bpida_solve.restype = ctypes.c_int
+    lib.bpida_solve_paths.argtypes = [P(ctypes.c_uint8), ctypes.c_int32, ctypes.c_int32,
+                                      P(ctypes.c_int32), P(ctypes.c_uint64), P(ctypes.c_uint8)]
+    lib.bpida_solve_paths.restype = ctypes.c_int
+    lib.bpida_solve_paths_device.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]
+    lib.bpida_solve_paths_device.restype = ctypes.c_int
     lib.bpida_solve_mixed.argtypes = [P(ctypes.c_uint8), P(ctypes.c_int32), ctypes.c_int32,
                                       P(ctypes.c_int32), P(ctypes.c_uint64)]
     lib.bpida_solve_mixed.restype = ctypes.c_int
@@ -122,6 +131,43 @@ def solve_raw(states: np.ndarray, width: int = 4):
                          out_len.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                          nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
     return int(rc), out_len, nodes
+
+
+def solve_paths_raw(states: np.ndarray, width: int = 4):
+    """Host-buffer entry with paths.  Returns (rc, out_len int32[n],
+    nodes uint64[n, 64], path uint8[n, 256]: moves U, L, R, D = 0..3, 0xFF
+    past the length)."""
+    st = np.ascontiguousarray(np.asarray(states, dtype=np.uint8).reshape(-1, width * width))
+    n = st.shape[0]
+    out_len = np.full(n, -7, np.int32)
+    nodes = np.zeros((n, MAX_THRESHOLDS), np.uint64)
+    path = np.zeros((n, MAX_PATH), np.uint8)
+    rc = lib.bpida_solve_paths(st.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), n, width,
+                               out_len.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                               path.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return int(rc), out_len, nodes, path
+
+
+def solve_paths_device(d_states, d_len, d_nodes, d_path, width: int = 4, stream=None) -> int:
+    """Device-buffer entry with paths on torch tensors (as ``solve_device``,
+    plus ``d_path`` uint8 [n, 256])."""
+    import torch  # device buffers and streams only
+
+    n = int(d_states.shape[0])
+    assert d_states.is_cuda and d_states.dtype == torch.uint8 and d_states.is_contiguous()
+    assert d_states.numel() == n * width * width
+    assert d_len.is_cuda and d_len.dtype == torch.int32 and d_len.numel() >= n
+    assert d_nodes.is_cuda and d_nodes.dtype in (torch.int64, torch.uint64)
+    assert d_nodes.is_contiguous() and d_nodes.numel() >= n * MAX_THRESHOLDS
+    assert d_path.is_cuda and d_path.dtype == torch.uint8 and d_path.is_contiguous()
+    assert d_path.numel() >= n * MAX_PATH
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(lib.bpida_solve_paths_device(ctypes.c_void_p(d_states.data_ptr()), n, width,
+                                            ctypes.c_void_p(d_len.data_ptr()),
+                                            ctypes.c_void_p(d_nodes.data_ptr()),
+                                            ctypes.c_void_p(d_path.data_ptr()),
+                                            ctypes.c_void_p(s.cuda_stream)))
 
 
 def solve_mixed_raw(states_list):

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbpida.so")
-SOURCES = ["bpida_kernels.hip", "bpida_batch.hip", "bpida_lb.hip", "bpida_host.hip"]
+SOURCES = ["bpida_kernels.hip", "bpida_batch.hip", "bpida_lb.hip", "bpida_path.hip", "bpida_host.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -20,6 +20,8 @@ FLAGS = [
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
+    # the split's level-size table is computed at compile time
+    "-fconstexpr-steps=16777216",
     "-I" + os.path.join(ROOT, "include"),
 ]
 

@@ -299,6 +299,8 @@ __device__ void complete_limit(const BatchArgs& A, int i, uint64_t* stage, uint1
         state = 1;
       } else if (fnext != L + 2) {
         state = -6;  // BPIDA_EINTERNAL
+      } else if (A.exact_limit) {
+        state = 2;  // one limit only, and no goal within it
       } else if (col + 1 >= 64 || L + 2 > A.max_limit) {
         state = -3;  // BPIDA_ELIMIT
       }
@@ -384,7 +386,7 @@ __device__ int64_t wave_split4(const Inst& I, int depth, const int32_t* walks, N
     base[0] = r;
   }
   WAVE_SYNC_MEM();
-  const int32_t* lc = walks + (size_t)I.blank * (kMaxDepth + 1);
+  const int32_t* lc = walks + walk_row(I.blank, 4);
   int gmin = INT_MAX;
   int64_t lvl = 0;
   for (int d = 0; d < depth; ++d) {
@@ -517,7 +519,7 @@ __device__ void admitter_loop(const BatchArgs& A, uint64_t* st, uint16_t* sm, ui
                                      const_cast<uint32_t*>(A.hist) + (size_t)slot * kHistBins,
                                      const_cast<int32_t*>(A.goal_g) + slot);
       S.root_off += r0;
-      S.nroots = V.walks[(size_t)I.blank * (kMaxDepth + 1) + V.depth];
+      S.nroots = V.walks[walk_row(I.blank, 4) + V.depth];
       if (S.limit > A.max_limit) S.done = -3;  // BPIDA_ELIMIT
     }
     if (lane == 0) A.is[slot] = S;
@@ -869,6 +871,13 @@ __global__ void batch_setup_kernel(BatchArgs A, const InstW* __restrict__ inst,
     S.limit = first_limit(inst[k].h0, A.start_limit);
     S.col = (S.limit - inst[k].h0) / 2;
     S.done = inst[k].status;  // 0 = to search
+    if (A.exact_limit) {
+      // one limit only: a limit below h0 or of the other parity has no path
+      // of exactly that length
+      S.limit = A.exact_limit[k];
+      S.col = 0;
+      if (S.done == 0 && (S.limit < inst[k].h0 || ((S.limit - inst[k].h0) & 1))) S.done = 2;
+    }
     S.outstanding = 0;
     S.nodes = 0;
     S.fmin = INT_MAX;
@@ -968,19 +977,20 @@ constexpr int kSplitThreadsW = 256;
 
 // The parent-pruned tree of one instance to depth D, level after level
 // (CreateRootSet, no duplicate elimination); the workgroup's instance has
-// width W.  Level sizes come from the walk-count table of that width.
+// width W and its start may not make move fb0 first (4: any move).  Level
+// sizes come from the walk-count table of that width.
 template <int W>
-__device__ void split_impl(const InstW& I, int depth, const int32_t* walks, NodeW* base,
+__device__ void split_impl(const InstW& I, int fb0, int depth, const int32_t* walks, NodeW* base,
                            uint32_t* h_lds, int32_t* fill, int32_t* gmin, int32_t* err,
                            int64_t* lvl_out) {
   using B = Board<W>;
   using S = typename B::S;
-  const int32_t* lc = walks + (size_t)I.blank * (kMaxDepth + 1);
+  const int32_t* lc = walks + walk_row(I.blank, fb0);
   if (threadIdx.x == 0) {
     NodeW r;
     r.lo = I.lo;
     r.hi = I.hi;
-    r.meta = node_meta(I.blank, 4, 0, I.h0);
+    r.meta = node_meta(I.blank, fb0, 0, I.h0);
     r.f = (uint32_t)I.h0;
     base[0] = r;
   }
@@ -1029,14 +1039,17 @@ __device__ void split_impl(const InstW& I, int depth, const int32_t* walks, Node
 }
 
 // One workgroup of 256 threads per instance; the instance's region is
-// tree_off[i] (or i * stride).  `walks` = [width - 3][cell][length] counts.
+// tree_off[i] (or i * stride).  `walks` = [width - 3][cell][first forbidden
+// move][length] counts; `forbid` (null: none) = per instance the move its
+// start may not make first (4: any).
 __global__ __launch_bounds__(kSplitThreadsW) void splitw_kernel(
     const InstW* __restrict__ inst, int depth, const int64_t* __restrict__ tree_off, int64_t stride,
-    const int32_t* __restrict__ walks, NodeW* __restrict__ tree, uint32_t* __restrict__ hist,
-    int32_t* __restrict__ goal_g, int32_t* __restrict__ err, int64_t* __restrict__ root_off,
-    int32_t* __restrict__ nroots) {
+    const int32_t* __restrict__ walks, const uint8_t* __restrict__ forbid, NodeW* __restrict__ tree,
+    uint32_t* __restrict__ hist, int32_t* __restrict__ goal_g, int32_t* __restrict__ err,
+    int64_t* __restrict__ root_off, int32_t* __restrict__ nroots) {
   const int i = blockIdx.x;
   const InstW I = inst[i];
+  const int fb0 = forbid ? min((int)forbid[i], 4) : 4;
   __shared__ uint32_t h_lds[kHistBins];
   __shared__ int32_t fill;
   __shared__ int32_t gmin;
@@ -1050,9 +1063,9 @@ __global__ __launch_bounds__(kSplitThreadsW) void splitw_kernel(
   int64_t lvl = 0;
   if (I.status == 0) {
     const int32_t* wk = walks + (size_t)(I.width - 3) * kWalkStride;
-    if (I.width == 3) split_impl<3>(I, depth, wk, base, h_lds, &fill, &gmin, err, &lvl);
-    else if (I.width == 4) split_impl<4>(I, depth, wk, base, h_lds, &fill, &gmin, err, &lvl);
-    else split_impl<5>(I, depth, wk, base, h_lds, &fill, &gmin, err, &lvl);
+    if (I.width == 3) split_impl<3>(I, fb0, depth, wk, base, h_lds, &fill, &gmin, err, &lvl);
+    else if (I.width == 4) split_impl<4>(I, fb0, depth, wk, base, h_lds, &fill, &gmin, err, &lvl);
+    else split_impl<5>(I, fb0, depth, wk, base, h_lds, &fill, &gmin, err, &lvl);
   } else {
     __syncthreads();
   }
@@ -1061,18 +1074,19 @@ __global__ __launch_bounds__(kSplitThreadsW) void splitw_kernel(
     goal_g[i] = gmin;
     root_off[i] = region + lvl;
     nroots[i] = I.status == 0
-                    ? walks[(size_t)(I.width - 3) * kWalkStride + (size_t)I.blank * (kMaxDepth + 1) + depth]
+                    ? walks[(size_t)(I.width - 3) * kWalkStride + walk_row(I.blank, fb0) + depth]
                     : 0;
   }
 }
 
 hipError_t launch_splitw(const InstW* d_inst, int n, int depth, const int64_t* d_tree_off,
-                         int64_t stride, const int32_t* d_walks, NodeW* d_tree, uint32_t* d_hist,
-                         int32_t* d_goal_g, int32_t* d_err, int64_t* d_root_off, int32_t* d_nroots,
-                         hipStream_t s) {
+                         int64_t stride, const int32_t* d_walks, const uint8_t* d_forbid,
+                         NodeW* d_tree, uint32_t* d_hist, int32_t* d_goal_g, int32_t* d_err,
+                         int64_t* d_root_off, int32_t* d_nroots, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(splitw_kernel, dim3(n), dim3(kSplitThreadsW), 0, s, d_inst, depth, d_tree_off,
-                     stride, d_walks, d_tree, d_hist, d_goal_g, d_err, d_root_off, d_nroots);
+                     stride, d_walks, d_forbid, d_tree, d_hist, d_goal_g, d_err, d_root_off,
+                     d_nroots);
   return hipGetLastError();
 }
 

@@ -96,7 +96,9 @@ struct Workspace {
   const int32_t* d_walks = nullptr;
   WalkTable h_walks = make_walk_table();
   DevBuf treew, winst, tree_offw, widths, byte_off;
-  DevBuf h2d_states, out_len, out_nodes;
+  DevBuf h2d_states, out_len, out_nodes, out_path;
+  // path reconstruction: current states, moves left, previous moves, probes
+  DevBuf p_cur, p_left, p_prev, p_probe, p_limit, p_forbid, p_len, p_nodes, p_status, p_err;
   DevBuf lb_load, lb_roots[2], lb_level, lb_count, lb_off, lb_avg, lb_total;
   LimitResult* h_res = nullptr;  // pinned
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -113,7 +115,7 @@ int map_err(hipError_t e) {
 // Number of non-backtracking blank walks of each length 0..depth from cell
 // `blank` of the 15-puzzle board (the exact size of each split-tree level).
 void level_sizes(int blank, int depth, int32_t* out) {
-  for (int d = 0; d <= depth; ++d) out[d] = g_ws.h_walks.v[1][blank][d];
+  for (int d = 0; d <= depth; ++d) out[d] = g_ws.h_walks.v[1][blank][4][d];
 }
 
 int ensure_device() {
@@ -358,9 +360,9 @@ void tree_size(const Workspace& W, int w, int D, int64_t* stride, int64_t* max_r
   *max_roots = 0;
   for (int c = 0; c < w * w; ++c) {
     int64_t tot = 0;
-    for (int d = 0; d <= D; ++d) tot += W.h_walks.v[w - 3][c][d];
+    for (int d = 0; d <= D; ++d) tot += W.h_walks.v[w - 3][c][4][d];
     *stride = std::max(*stride, tot);
-    *max_roots = std::max<int64_t>(*max_roots, W.h_walks.v[w - 3][c][D]);
+    *max_roots = std::max<int64_t>(*max_roots, W.h_walks.v[w - 3][c][4][D]);
   }
 }
 
@@ -543,7 +545,8 @@ int alloc_batched(const BatchPlan& P, BatchBufs* B) {
 int enqueue_batched_into(const uint8_t* d_states, int32_t* d_len, uint64_t* d_nodes,
                          int32_t* d_status, hipStream_t st, const Options& O, const BatchPlan& P,
                          const BatchBufs& B, const int32_t* walks, const int32_t* h_widths,
-                         hipEvent_t ev0, hipEvent_t ev1, int wall_khz) {
+                         hipEvent_t ev0, hipEvent_t ev1, int wall_khz,
+                         const int32_t* exact_limit = nullptr, const uint8_t* root_forbid = nullptr) {
   hipError_t e;
 #define HIPCHK(x)              \
   do {                         \
@@ -564,8 +567,8 @@ int enqueue_batched_into(const uint8_t* d_states, int32_t* d_len, uint64_t* d_no
   HIPCHK(launch_ingestw(d_states, h_widths ? B.byte_off : nullptr, h_widths ? B.widths : nullptr,
                         P.width, n, B.winst, st));
   HIPCHK(launch_zero_i32(B.err, 1, st));
-  HIPCHK(launch_splitw(B.winst, n, P.D, h_widths ? B.tree_offw : nullptr, P.stride, walks, B.treew,
-                       B.hist, B.goal_g, B.err, B.root_off, B.nroots, st));
+  HIPCHK(launch_splitw(B.winst, n, P.D, h_widths ? B.tree_offw : nullptr, P.stride, walks, root_forbid,
+                       B.treew, B.hist, B.goal_g, B.err, B.root_off, B.nroots, st));
   HIPCHK(launch_zero_words(B.qctl, sizeof(QueueCtl), st));
 
   BatchArgs A;
@@ -593,6 +596,7 @@ int enqueue_batched_into(const uint8_t* d_states, int32_t* d_len, uint64_t* d_no
   A.start_limit = (int32_t)O.start_threshold;
   A.seed_chunk = P.sc;
   A.push_spin = (int32_t)O.push_spin;
+  A.exact_limit = exact_limit;
   HIPCHK(launch_batch_setup(A, B.winst, B.root_off, B.nroots, st));
   if (ev0) HIPCHK(hipEventRecord(ev0, st));
   HIPCHK(launch_batch4(P.cap, P.npl, P.wpg, (int)P.grid, A, st));
@@ -673,6 +677,77 @@ int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_node
 #undef HIPCHK
 }
 
+// One optimal path per instance: the batched solve, then one round of
+// exact-limit probes per move (bpida_path.hip).  Probes of a round run as one
+// batched solve of 4 n boards, each at the single limit (moves left - 1),
+// with the move back to the parent forbidden at its root and the search
+// stopping at its first goal.  Statistics stay those of the solve.
+int run_paths(const uint8_t* d_states, int n, int width, int32_t* d_len, uint64_t* d_nodes,
+              uint8_t* d_path, hipStream_t st, const Options& O) {
+  Workspace& W = g_ws;
+  hipError_t e;
+#define HIPCHK(x)              \
+  do {                         \
+    e = (x);                   \
+    if (e != hipSuccess) {     \
+      (void)hipGetLastError(); \
+      return map_err(e);       \
+    }                          \
+  } while (0)
+  Options Ob = O;
+  Ob.mode = kModeBatched;
+  const int rc = run_batched(d_states, n, d_len, d_nodes, st, Ob, width);
+  uint64_t solve_stats[16];
+  memcpy(solve_stats, g_stats, sizeof solve_stats);
+  if (n == 0) return rc;
+  const int nn = width * width;
+  std::vector<int32_t> len((size_t)n);
+  HIPCHK(hipMemcpyAsync(len.data(), d_len, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int maxlen = 0;
+  for (int i = 0; i < n; ++i) maxlen = std::max(maxlen, (int)len[i]);
+  const size_t np = 4 * (size_t)n;
+  if (W.p_cur.ensure((size_t)n * nn) != hipSuccess || W.p_left.ensure(sizeof(int32_t) * (size_t)n) != hipSuccess ||
+      W.p_prev.ensure((size_t)n) != hipSuccess || W.p_probe.ensure(np * nn) != hipSuccess ||
+      W.p_limit.ensure(sizeof(int32_t) * np) != hipSuccess || W.p_forbid.ensure(np) != hipSuccess ||
+      W.p_len.ensure(sizeof(int32_t) * np) != hipSuccess ||
+      W.p_nodes.ensure(sizeof(uint64_t) * BPIDA_MAX_THRESHOLDS * np) != hipSuccess ||
+      W.p_status.ensure(sizeof(int32_t) * np) != hipSuccess || W.p_err.ensure(sizeof(int32_t)) != hipSuccess)
+    return BPIDA_ENOMEM;
+  HIPCHK(launch_path_init(d_states, d_len, n, nn, W.p_cur.as<uint8_t>(), W.p_left.as<int32_t>(),
+                          W.p_prev.as<uint8_t>(), d_path, st));
+  HIPCHK(launch_zero_i32(W.p_err.as<int32_t>(), 1, st));
+  Options Op = Ob;
+  Op.first_solution = 1;
+  Op.start_threshold = -1;
+  Op.max_threshold = -1;
+  BatchPlan P;
+  int prc = plan_batched((int)np, width, nullptr, Op, W.num_cu, &P);
+  if (prc != BPIDA_OK) return prc;
+  BatchBufs B;
+  prc = alloc_batched(P, &B);
+  if (prc != BPIDA_OK) return prc;
+  for (int step = 0; step < maxlen; ++step) {
+    HIPCHK(launch_path_probe(W.p_cur.as<uint8_t>(), W.p_left.as<int32_t>(), W.p_prev.as<uint8_t>(), n,
+                             width, W.p_probe.as<uint8_t>(), W.p_limit.as<int32_t>(),
+                             W.p_forbid.as<uint8_t>(), st));
+    prc = enqueue_batched_into(W.p_probe.as<uint8_t>(), W.p_len.as<int32_t>(), W.p_nodes.as<uint64_t>(),
+                               W.p_status.as<int32_t>(), st, Op, P, B, W.d_walks, nullptr, nullptr,
+                               nullptr, W.wall_khz, W.p_limit.as<int32_t>(), W.p_forbid.as<uint8_t>());
+    if (prc != BPIDA_OK) return prc;
+    HIPCHK(launch_path_select(W.p_probe.as<uint8_t>(), W.p_status.as<int32_t>(), d_len, n, nn,
+                              W.p_cur.as<uint8_t>(), W.p_left.as<int32_t>(), W.p_prev.as<uint8_t>(),
+                              d_path, W.p_err.as<int32_t>(), st));
+  }
+  int32_t perr = 0;
+  HIPCHK(hipMemcpyAsync(&perr, W.p_err.p, sizeof perr, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  memcpy(g_stats, solve_stats, sizeof solve_stats);
+  if (perr) return rc != BPIDA_OK ? rc : BPIDA_EINTERNAL;
+  return rc;
+#undef HIPCHK
+}
+
 int check_opts(int width) {
   if (width < BPIDA_MIN_WIDTH || width > BPIDA_MAX_WIDTH) return BPIDA_EINVAL;
   return BPIDA_OK;
@@ -710,6 +785,62 @@ extern "C" int bpida_solve(const uint8_t* states, int32_t n_instances, int32_t w
         hipStreamSynchronize(st) != hipSuccess)
       return BPIDA_EDEVICE;
     return rc;
+  } catch (const std::bad_alloc&) {
+    return BPIDA_ENOMEM;
+  } catch (...) {
+    return BPIDA_EINTERNAL;
+  }
+}
+
+extern "C" int bpida_solve_paths(const uint8_t* states, int32_t n_instances, int32_t width,
+                                 int32_t* out_len, uint64_t* out_nodes_per_threshold, uint8_t* out_path) {
+  try {
+    if (!states || !out_len || !out_nodes_per_threshold || !out_path || n_instances < 0)
+      return BPIDA_EINVAL;
+    if (check_opts(width) != BPIDA_OK) return BPIDA_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    const Options O = g_opt;
+    const size_t n = (size_t)n_instances;
+    if (n == 0) return BPIDA_OK;
+    int rc = ensure_device();
+    if (rc != BPIDA_OK) return rc;
+    Workspace& W = g_ws;
+    hipStream_t st = nullptr;
+    const size_t bytes = n * (size_t)width * (size_t)width;
+    if (W.h2d_states.ensure(bytes) != hipSuccess || W.out_len.ensure(n * sizeof(int32_t)) != hipSuccess ||
+        W.out_nodes.ensure(n * BPIDA_MAX_THRESHOLDS * sizeof(uint64_t)) != hipSuccess ||
+        W.out_path.ensure(n * BPIDA_MAX_PATH) != hipSuccess)
+      return BPIDA_ENOMEM;
+    if (hipMemcpyAsync(W.h2d_states.p, states, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+      return BPIDA_EDEVICE;
+    rc = run_paths(W.h2d_states.as<uint8_t>(), (int)n, width, W.out_len.as<int32_t>(),
+                   W.out_nodes.as<uint64_t>(), W.out_path.as<uint8_t>(), st, O);
+    if (hipMemcpyAsync(out_len, W.out_len.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(out_nodes_per_threshold, W.out_nodes.p, n * BPIDA_MAX_THRESHOLDS * sizeof(uint64_t),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(out_path, W.out_path.p, n * BPIDA_MAX_PATH, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return BPIDA_EDEVICE;
+    return rc;
+  } catch (const std::bad_alloc&) {
+    return BPIDA_ENOMEM;
+  } catch (...) {
+    return BPIDA_EINTERNAL;
+  }
+}
+
+extern "C" int bpida_solve_paths_device(const uint8_t* d_states, int32_t n_instances, int32_t width,
+                                        int32_t* d_len, uint64_t* d_nodes, uint8_t* d_path,
+                                        void* hip_stream) {
+  try {
+    if (!d_states || !d_len || !d_nodes || !d_path || n_instances < 0) return BPIDA_EINVAL;
+    if (check_opts(width) != BPIDA_OK) return BPIDA_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    const Options O = g_opt;
+    if (n_instances == 0) return BPIDA_OK;
+    int rc = ensure_device();
+    if (rc != BPIDA_OK) return rc;
+    return run_paths(d_states, n_instances, width, d_len, d_nodes, d_path, (hipStream_t)hip_stream, O);
   } catch (const std::bad_alloc&) {
     return BPIDA_ENOMEM;
   } catch (...) {

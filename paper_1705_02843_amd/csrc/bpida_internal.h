@@ -123,25 +123,34 @@ struct LimitResult {
 };
 
 constexpr int kHistBins = 256;  // f values 0..255 of the split tree's interior
+constexpr int kMaxPath = 256;   // moves per returned path (limits stay below 256)
 constexpr int kMaxLimit = 255;  // slack and f fit in 8 bits
 constexpr int kMaxDepth = 16;  // deepest root split
-constexpr int kWalkCells = 25;  // walk-count table: [width - 3][cell][length]
-constexpr int kWalkStride = kWalkCells * (kMaxDepth + 1);
+constexpr int kWalkCells = 25;  // walk-count table: [width - 3][cell][first forbidden move][length]
+constexpr int kWalkStride = kWalkCells * 5 * (kMaxDepth + 1);
 
-// Exact split-tree level sizes: v[w - 3][c][d] = number of blank walks of
+// Exact split-tree level sizes: v[w - 3][c][f][d] = number of blank walks of
 // length d from cell c of a width-w board that never undo their previous
-// move (every level of the parent-pruned tree, no duplicate elimination).
+// move and whose first move is not f (f = 4: any first move): every level of
+// the parent-pruned tree of a root with forbidden move f, no duplicate
+// elimination.
 struct WalkTable {
-  int32_t v[3][kWalkCells][kMaxDepth + 1];
+  int32_t v[3][kWalkCells][5][kMaxDepth + 1];
 };
+
+// Offset of the row (cell, first forbidden move) inside one width's table.
+__host__ __device__ constexpr int walk_row(int cell, int forbid) {
+  return (cell * 5 + forbid) * (kMaxDepth + 1);
+}
 
 constexpr WalkTable make_walk_table() {
   WalkTable t{};
   for (int w = 3; w <= 5; ++w)
-    for (int blank = 0; blank < w * w; ++blank) {
+    for (int blank = 0; blank < w * w; ++blank)
+      for (int f0 = 0; f0 <= 4; ++f0) {
       // cur[c][f]: walks ending at cell c whose next move may not be f (4: any)
       int64_t cur[kWalkCells][5] = {};
-      cur[blank][4] = 1;
+      cur[blank][f0] = 1;
       for (int d = 0; d <= kMaxDepth; ++d) {
         int64_t tot = 0, nxt[kWalkCells][5] = {};
         for (int c = 0; c < w * w; ++c)
@@ -157,7 +166,7 @@ constexpr WalkTable make_walk_table() {
               nxt[n][3 - a] += m;
             }
           }
-        t.v[w - 3][blank][d] = (int32_t)(tot < INT32_MAX ? tot : INT32_MAX);
+        t.v[w - 3][blank][f0][d] = (int32_t)(tot < INT32_MAX ? tot : INT32_MAX);
         for (int c = 0; c < kWalkCells; ++c)
           for (int fb = 0; fb < 5; ++fb) cur[c][fb] = nxt[c][fb];
       }
@@ -199,7 +208,8 @@ struct SlotCtl {
 struct InstState {
   int32_t limit;        // current f-limit
   int32_t col;          // output column of the current limit
-  int32_t done;         // 0 searching, 1 solved, < 0 bpida_status
+  int32_t done;         // 0 searching, 1 solved, 2 no goal within an exact limit,
+                        // < 0 bpida_status
   int32_t outstanding;  // chunks queued or held at the current limit
   uint64_t nodes;       // nodes expanded by the search at the current limit
   int32_t fmin;         // smallest pruned f at the current limit
@@ -288,6 +298,8 @@ struct BatchArgs {
   int32_t first_solution; // nonzero: the final limit stops at its first goal
   int32_t start_limit;    // first f-limit to search (< 0: h0)
   int32_t seed_chunk;     // roots per seeded chunk (8..64)
+  const int32_t* exact_limit;  // null, or per instance the one f-limit to search
+                               // (status 1: a goal within it, 2: none)
   int32_t push_spin;     // polls of a full slot before a push gives its ticket up
   int32_t server;        // nonzero: continuous-batching server (srv below)
   ServerArgs srv;
@@ -303,13 +315,24 @@ hipError_t launch_batch_setup(const BatchArgs& A, const InstW* d_inst, const int
 hipError_t launch_ingestw(const uint8_t* d_states, const int64_t* d_byte_off, const int32_t* d_widths,
                           int width, int n, InstW* d_inst, hipStream_t s);
 hipError_t launch_splitw(const InstW* d_inst, int n, int depth, const int64_t* d_tree_off,
-                         int64_t stride, const int32_t* d_walks, NodeW* d_tree, uint32_t* d_hist,
-                         int32_t* d_goal_g, int32_t* d_err, int64_t* d_root_off, int32_t* d_nroots,
-                         hipStream_t s);
+                         int64_t stride, const int32_t* d_walks, const uint8_t* d_forbid,
+                         NodeW* d_tree, uint32_t* d_hist, int32_t* d_goal_g, int32_t* d_err,
+                         int64_t* d_root_off, int32_t* d_nroots, hipStream_t s);
 hipError_t launch_batch4(int lds_cap, int npl, int wpg, int grid, const BatchArgs& A, hipStream_t s);
 hipError_t launch_batch_status(const InstState* d_is, int n, const QueueCtl* d_q,
                                const int32_t* d_split_err, int32_t* d_status, hipStream_t s);
 int batch4_max_blocks_per_cu(int lds_cap, int npl, int wpg);
+
+// Path reconstruction by exact-limit probes (bpida_path.hip).
+hipError_t launch_path_init(const uint8_t* d_states, const int32_t* d_len, int n, int nn,
+                            uint8_t* d_cur, int32_t* d_left, uint8_t* d_prev, uint8_t* d_path,
+                            hipStream_t s);
+hipError_t launch_path_probe(const uint8_t* d_cur, const int32_t* d_left, const uint8_t* d_prev, int n,
+                             int w, uint8_t* d_probe, int32_t* d_probe_limit, uint8_t* d_probe_forbid,
+                             hipStream_t s);
+hipError_t launch_path_select(const uint8_t* d_probe, const int32_t* d_status, const int32_t* d_len,
+                              int n, int nn, uint8_t* d_cur, int32_t* d_left, uint8_t* d_prev,
+                              uint8_t* d_path, int32_t* d_err, hipStream_t s);
 
 // Kernel launchers (bpida_kernels.hip).
 hipError_t launch_ingest4(const uint8_t* d_states, int n, Inst* d_inst, hipStream_t s);

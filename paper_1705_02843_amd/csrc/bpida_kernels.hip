@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kSplitThreads) void split4_kernel(
     }
     return;
   }
-  const int32_t* lc = walks + (size_t)I.blank * (kMaxDepth + 1);
+  const int32_t* lc = walks + walk_row(I.blank, 4);
   if (threadIdx.x == 0) {
     Node r;
     r.tiles = I.tiles;

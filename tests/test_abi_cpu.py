@@ -63,6 +63,14 @@ def test_argument_errors_before_device_work(B):
                                           ctypes.c_void_p(8), None) == B.EINVAL
     assert B.lib.bpida_solve_mixed_device(ctypes.c_void_p(8), wp, 0, ctypes.c_void_p(8),
                                           ctypes.c_void_p(8), None) == B.OK
+    pp = np.zeros(256, np.uint8).ctypes.data_as(P(ctypes.c_uint8))
+    assert B.lib.bpida_solve_paths(sp, 1, 4, lp, npp, None) == B.EINVAL
+    assert B.lib.bpida_solve_paths(None, 1, 4, lp, npp, pp) == B.EINVAL
+    assert B.lib.bpida_solve_paths(sp, 1, 2, lp, npp, pp) == B.EINVAL
+    assert B.lib.bpida_solve_paths(sp, 0, 4, lp, npp, pp) == B.OK
+    v8 = ctypes.c_void_p(8)
+    assert B.lib.bpida_solve_paths_device(v8, 1, 4, v8, v8, None, None) == B.EINVAL
+    assert B.lib.bpida_solve_paths_device(v8, 0, 4, v8, v8, v8, None) == B.OK
     for fn in (B.lib.bpida_solve_device_async, B.lib.bpida_solve_device_noalloc):
         v = ctypes.c_void_p(8)
         assert fn(None, 1, 4, v, v, v, None) == B.EINVAL
