@@ -236,6 +236,27 @@ def first_solution_leg(bpida, part, states, width, d_states, d_len, d_nodes, str
     return res
 
 
+def valu_issue_probe():
+    """The integer VALU issue rate measured on this device: independent
+    32-bit add chains in every lane of 16384 waves (libvalu_probe.so, built
+    with the library).  None if the probe is not built."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_1705_02843_amd", "libvalu_probe.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    lib.bpida_valu_probe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.bpida_valu_probe.restype = ctypes.c_int
+    rate, ms = ctypes.c_double(0), ctypes.c_double(0)
+    rc = lib.bpida_valu_probe(4096, 20000, ctypes.byref(rate), ctypes.byref(ms))
+    if rc != 0:
+        return None
+    return {"wave64_valu_per_s": round(rate.value, 1), "gops": round(rate.value * 64 / 1e9, 1),
+            "ms": round(ms.value, 3),
+            "note": "independent v_add_u32 chains, 4096 workgroups of 4 waves"}
+
+
 def load_traffic(src_hash, mode, workload):
     """The committed rocprofv3 counter record of the timed search kernel (HBM
     bytes per launch, VALU busy, active lanes), if it was taken on the
@@ -373,6 +394,9 @@ def main():
     avg_launch_s = (search_us / launches) * 1e-6 if launches else float("nan")
     ops_per_launch = search_nodes * OPS_PER_NODE / launches if launches else 0.0
     achieved = ops_per_launch / avg_launch_s / 1e9 if launches else 0.0
+    # algorithmic HBM bytes per launch: 16 per split-tree root read per limit
+    # (8 bytes of state, 8 of bookkeeping); the search itself stays on chip
+    algo_bytes = (16 * acc.get("roots_read", 0) // launches) if launches else None
     src_hash = kernel_source_hash()
     counters = load_traffic(src_hash, args.mode, args.workload)
     traffic = counters.get("bytes_per_launch") if counters else None
@@ -413,6 +437,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 1), "peak": round(PEAK_INT_GOPS, 1),
                      "unit": "Gop/s", "frac": round(achieved / PEAK_INT_GOPS, 4),
                      "traffic": traffic,
+                     "algorithmic_bytes": algo_bytes,
+                     "traffic_over_algorithmic": (round(traffic / algo_bytes, 2)
+                                                  if traffic and algo_bytes else None),
                      "kernel": kname,
                      "ops_per_node": OPS_PER_NODE,
                      "avg_launch_us": round(avg_launch_s * 1e6, 2),
@@ -433,19 +460,29 @@ def main():
                           "queue_frac": round(acc["wg_us_queue"] / wg_total, 4),
                           "chunks_donated_per_step": acc["chunks_pushed"] // max(1, args.steps)}
     if not args.no_compare and widths is None:
-        other = "plain" if args.mode == "batched" else "batched"
+        # the other mode on the same states: for batched, plain BPIDA* (one
+        # launch per instance and limit) with Alg. 1's 16-node lane map and
+        # with the batched kernel's 64-node round, so that the batching win
+        # and the round's own win are stated apart
+        legs = ([("plain16", "plain", 16), ("plain64", "plain", 64)] if args.mode == "batched"
+                else [("batched", "batched", 16)])
         saved = {k: bpida.get_option(k) for k in ("frontier_depth", "lds_stack_capacity",
-                                                  "max_workgroups")}
-        _, _, oacc = run_mode(other, args.compare_steps, 1)
-        for k, v in saved.items():
-            bpida.set_option(k, v)
-        odt = oacc["median_step_s"]
-        out["compare"] = {"mode": other, "value": round(nodes_per_step / odt, 1),
-                          "unit": "nodes/s", "ms_per_step_median": round(odt * 1e3, 3),
-                          "instances_per_s": round(n / odt, 2), "steps": args.compare_steps,
-                          "warmup": 1,
-                          "speedup_of_instances_per_s": round(
-                              (n * args.steps / dt) / (n / odt), 3)}
+                                                  "max_workgroups", "plain_nodes_per_round")}
+        out["compare"] = {}
+        for tag, other, pnpl in legs:
+            bpida.set_option("plain_nodes_per_round", pnpl)
+            _, _, oacc = run_mode(other, args.compare_steps, 1)
+            for k, v in saved.items():
+                bpida.set_option(k, v)
+            odt = oacc["median_step_s"]
+            oshare = (oacc["search_nodes"] / (oacc["search_us"] * 1e-6)) if oacc["search_us"] else None
+            out["compare"][tag] = {
+                "mode": other, "value": round(nodes_per_step / odt, 1), "unit": "nodes/s",
+                "ms_per_step_median": round(odt * 1e3, 3), "instances_per_s": round(n / odt, 2),
+                "steps": args.compare_steps, "warmup": 1,
+                "search_nodes_per_s_in_kernel": round(oshare, 1) if oshare else None,
+                "launches_per_step": oacc["launches"] // max(1, args.compare_steps),
+                "speedup_of_instances_per_s": round((n * args.steps / dt) / (n / odt), 3)}
         bpida.set_option("mode", MODES[args.mode])
     if args.mode == "batched" and not args.kernel_only:
         # the host-buffer entry (PCIe copies in and out included), beside `value`
@@ -469,6 +506,10 @@ def main():
     if args.mode == "batched" and widths is None and not args.no_first_solution:
         out["first_solution"] = first_solution_leg(bpida, parts[0], states, width, d_states, d_len,
                                                    d_nodes, stream, not args.no_cpu_baseline)
+    probe = valu_issue_probe()
+    if probe:
+        out["roofline"]["peak_measured"] = probe
+        out["roofline"]["frac_of_measured"] = round(achieved / probe["gops"], 4)
     if not args.no_cpu_baseline:
         nthreads, aff, nproc = host_threads()
         progress("oracle on %d host threads" % nthreads)

@@ -359,7 +359,10 @@ int64_t bpida_get_option(const char *key);
  *          32 LDS stack overrun, 256 split check)
  *   out[14] batched mode: work-queue slots (chunks of 64 entries)
  *   out[15] plain mode: roots added by the static load balancing
- * n = number of slots to fill (<= 16).  Returns BPIDA_OK or BPIDA_EINVAL.
+ *   out[16] split-tree roots read (once per root and searched limit: the
+ *          algorithmic HBM reads of the search, 16 bytes each)
+ *   out[17] batched mode: 5x5 chunks taken from the work queue
+ * n = number of slots to fill (<= 20).  Returns BPIDA_OK or BPIDA_EINVAL.
  */
 int bpida_last_stats(uint64_t *out, int32_t n);
 

@@ -111,13 +111,14 @@ def get_option(key: str) -> int:
 
 
 def last_stats() -> dict:
-    out = (ctypes.c_uint64 * 16)()
-    rc = lib.bpida_last_stats(out, 16)
+    out = (ctypes.c_uint64 * 20)()
+    rc = lib.bpida_last_stats(out, 20)
     if rc != OK:
         raise BpidaError(rc, "last_stats")
     keys = ("rounds", "search_nodes", "spilled", "launches", "search_us", "spill_high_water",
             "chunks_pushed", "chunks_popped", "wg_us_search", "wg_us_queue", "wg_us_idle",
-            "donations_voluntary", "grid", "error_bits", "queue_slots", "lb_roots_added")
+            "donations_voluntary", "grid", "error_bits", "queue_slots", "lb_roots_added",
+            "roots_read", "wide_chunks_taken")
     return {k: int(out[i]) for i, k in enumerate(keys)}
 
 

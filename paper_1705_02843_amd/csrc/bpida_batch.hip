@@ -160,7 +160,9 @@ __device__ bool q_take(const BatchArgs& A, uint64_t& ticket, uint64_t& tile, uin
   count = wave_bcast(c->count);
   inst = wave_bcast(c->inst);
   // the high words only for a 5x5 chunk: a 4x4 chunk reads 6 lines, not 10
-  hi = wave_bcast(c->wide) ? A.hi[(ticket & mask) * kQChunk + lane] : 0ull;
+  const int wide = wave_bcast(c->wide);
+  hi = wide ? A.hi[(ticket & mask) * kQChunk + lane] : 0ull;
+  if (wide && lane == 0) __hip_atomic_fetch_add(&q->chunks_read_wide, (uint64_t)1, __ATOMIC_RELAXED, AGENT);
   WAVE_SYNC_MEM();  // all lanes have read the slot before it is handed back
   if (lane == 0)
     __hip_atomic_store(&A.seq[ticket & mask].seq, 4 * (ticket + mask + 1), __ATOMIC_RELEASE, AGENT);
@@ -238,6 +240,7 @@ __device__ bool seed_limit(const BatchArgs& A, int i, uint64_t* stage, uint16_t*
   fm = wave_min(fm);
   int last = 0;
   if (lane == 0) {
+    if (nroots) __hip_atomic_fetch_add(&A.q->roots_read, (uint64_t)nroots, __ATOMIC_RELAXED, AGENT);
     if (fm != INT_MAX) __hip_atomic_fetch_min(&S->fmin, fm, __ATOMIC_RELAXED, AGENT);
     last = __hip_atomic_fetch_add(&S->outstanding, -1, __ATOMIC_ACQ_REL, AGENT) == 1;
   }

@@ -49,7 +49,8 @@ struct Options {
 
 std::mutex g_mu;  // serialises solves and option changes
 Options g_opt;
-uint64_t g_stats[16] = {0};
+constexpr int kStats = 20;
+uint64_t g_stats[kStats] = {0};
 
 // Set while the caller's stream is capturing a graph: buffers may not grow.
 bool g_no_alloc = false;
@@ -170,7 +171,7 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
   if (O.mode == kModeBatched) return run_batched(d_states, n, d_len, d_nodes, st, O, width);
   if (width != 4) return BPIDA_EINVAL;  // the plain path is the 15-puzzle kernel
   Workspace& W = g_ws;
-  uint64_t stats[16] = {0};
+  uint64_t stats[kStats] = {0};
   hipError_t e;
 #define HIPCHK(x)              \
   do {                         \
@@ -294,6 +295,7 @@ int run_plain(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes,
         stats[1] += R.searched;
         stats[2] += R.spilled;
         stats[3] += grid > 0 ? 1 : 0;
+        stats[16] += (uint64_t)nroots;  // every root is read once per limit
         stats[5] = std::max<uint64_t>(stats[5], (uint64_t)R.spill_hw);
         if (R.err) {
           code = BPIDA_ENOMEM;
@@ -627,7 +629,7 @@ int enqueue_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_
 int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_nodes, hipStream_t st,
                 const Options& O, int width, const int32_t* h_widths) {
   Workspace& W = g_ws;
-  uint64_t stats[16] = {0};
+  uint64_t stats[kStats] = {0};
   hipError_t e;
 #define HIPCHK(x)              \
   do {                         \
@@ -669,6 +671,8 @@ int run_batched(const uint8_t* d_states, int n, int32_t* d_len, uint64_t* d_node
   stats[12] = (uint64_t)grid;
   stats[13] = (uint64_t)(uint32_t)qc.err | ((uint64_t)(split_err != 0) << 8);
   stats[14] = W.qcap;
+  stats[16] = qc.roots_read;
+  stats[17] = qc.chunks_read_wide;
   memcpy(g_stats, stats, sizeof stats);
   int rc = BPIDA_OK;
   for (int i = 0; i < n && rc == BPIDA_OK; ++i)
@@ -697,7 +701,7 @@ int run_paths(const uint8_t* d_states, int n, int width, int32_t* d_len, uint64_
   Options Ob = O;
   Ob.mode = kModeBatched;
   const int rc = run_batched(d_states, n, d_len, d_nodes, st, Ob, width);
-  uint64_t solve_stats[16];
+  uint64_t solve_stats[kStats];
   memcpy(solve_stats, g_stats, sizeof solve_stats);
   if (n == 0) return rc;
   const int nn = width * width;
@@ -1132,7 +1136,7 @@ extern "C" int bpida_server_stop(void) {
       return BPIDA_EDEVICE;
     }
     V.running = false;
-    uint64_t stats[16] = {0};
+    uint64_t stats[kStats] = {0};
     stats[0] = qc.rounds;
     stats[1] = qc.searched;
     stats[2] = qc.pushes * kQChunk;
@@ -1283,7 +1287,7 @@ extern "C" int64_t bpida_get_option(const char* key) {
 }
 
 extern "C" int bpida_last_stats(uint64_t* out, int32_t n) {
-  if (!out || n < 0 || n > 16) return BPIDA_EINVAL;
+  if (!out || n < 0 || n > kStats) return BPIDA_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   for (int i = 0; i < n; ++i) out[i] = g_stats[i];
   return BPIDA_OK;

@@ -236,6 +236,8 @@ struct QueueCtl {
   uint64_t t_work, t_queue, t_idle;  // wall-clock ticks summed over workgroups
   uint64_t voluntary;                // donations made because workgroups idled
   uint64_t qmax;                     // most chunks queued at once (seen at a push)
+  uint64_t roots_read;               // split-tree roots read while seeding limits
+  uint64_t chunks_read_wide;         // 5x5 chunks taken (their high words read too)
 };
 
 // ---------------------------------------------------------------------------
