@@ -237,24 +237,33 @@ def first_solution_leg(bpida, part, states, width, d_states, d_len, d_nodes, str
 
 
 def valu_issue_probe():
-    """The integer VALU issue rate measured on this device: independent
-    32-bit add chains in every lane of 16384 waves (libvalu_probe.so, built
-    with the library).  None if the probe is not built."""
+    """The integer VALU issue rates measured on this device, per instruction
+    class: independent chains in every lane of 16384 waves
+    (libvalu_probe.so, built with the library).  ``gops`` is the class the
+    search round consists of (three-operand, 64-bit, multiply, mbcnt,
+    compare and select instructions, timed with v_bfe_u32); the simple
+    two-operand class (timed with v_add_u32) issues faster.  None if the
+    probe is not built."""
     import ctypes
     path = os.path.join(ROOT, "paper_1705_02843_amd", "libvalu_probe.so")
     if not os.path.exists(path):
         return None
     lib = ctypes.CDLL(path)
-    lib.bpida_valu_probe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
-                                     ctypes.POINTER(ctypes.c_double)]
+    lib.bpida_valu_probe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.bpida_valu_probe.restype = ctypes.c_int
-    rate, ms = ctypes.c_double(0), ctypes.c_double(0)
-    rc = lib.bpida_valu_probe(4096, 20000, ctypes.byref(rate), ctypes.byref(ms))
-    if rc != 0:
-        return None
-    return {"wave64_valu_per_s": round(rate.value, 1), "gops": round(rate.value * 64 / 1e9, 1),
-            "ms": round(ms.value, 3),
-            "note": "independent v_add_u32 chains, 4096 workgroups of 4 waves"}
+    res = {}
+    for kind, tag in ((1, "bfe_class"), (0, "add_class")):
+        rate, ms = ctypes.c_double(0), ctypes.c_double(0)
+        if lib.bpida_valu_probe(kind, 4096, 20000, ctypes.byref(rate), ctypes.byref(ms)) != 0:
+            return None
+        res[tag] = {"wave64_valu_per_s": round(rate.value, 1),
+                    "per_cu_clock_at_2_4_ghz": round(rate.value / (256 * 2.4e9), 3),
+                    "gops": round(rate.value * 64 / 1e9, 1)}
+    res["gops"] = res["bfe_class"]["gops"]
+    res["note"] = ("independent chains, 4096 workgroups of 4 waves; the round's instructions are "
+                   "of the bfe class")
+    return res
 
 
 def load_traffic(src_hash, mode, workload):
@@ -426,6 +435,7 @@ def main():
                    "frontier_depth": bpida.get_option("frontier_depth"),
                    "lds_stack_capacity": bpida.get_option("lds_stack_capacity"),
                    "nodes_per_round": bpida.get_option("nodes_per_round"),
+                   "wg_size": bpida.get_option("wg_size"),
                    "max_workgroups": bpida.get_option("max_workgroups"),
                    "donate_every": bpida.get_option("donate_every"),
                    "donate_min": bpida.get_option("donate_min"),

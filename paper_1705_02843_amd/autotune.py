@@ -1,18 +1,19 @@
-"""Autotuner for the batched search: sweeps the launch options on a workload,
-checks that every configuration returns identical results, and writes the
-fastest configuration to a JSON table keyed by (architecture, width, batch
-size class).
+"""Autotuner for the batched search: searches the launch options on a
+workload, checks that every configuration returns identical results, and
+writes the fastest configuration to a JSON table keyed by (architecture,
+width, batch size class).
 
-    python -m paper_1705_02843_amd.autotune --workload c2_md30_38
+    python -m paper_1705_02843_amd.autotune --workload c3_uneven
 
-Options swept: nodes per round (16: four lanes per node, Alg. 1's map; 64:
-one node per lane), LDS ring capacity, root split depth D, the size of the
-persistent grid (the occupancy limit or half of it), and the donation policy
-(rounds between checks, smallest donating stack, entries per donated chunk).
-The workgroup is always one wave64 (Alg. 1's block = one SIMD unit, so the
-round needs no barrier); the lanes-per-node choice (nodes per round) is the
-workgroup-shape axis.  Large batches sweep a
-smaller set, since one solve takes seconds.  Mixed-width workloads are keyed
+Axes: nodes per round with the LDS stack capacity (16: four lanes per node,
+Alg. 1's map; 64: one node per lane), the workgroup size (64, 128 or 256
+threads: 1, 2 or 4 independent waves, Sec. 5's block = one wave, several
+per workgroup), the root split depth D (4..10), the size of the persistent
+grid (the occupancy limit or half of it), and the donation policy (rounds
+between checks, smallest donating stack, entries per donated chunk).  The
+search is coordinate descent: starting from the stored or the library's
+options, each axis in turn is swept with the others fixed and the fastest
+value kept, for two passes over all axes.  Mixed-width workloads are keyed
 "mixed" instead of by width.
 """
 from __future__ import annotations
@@ -26,7 +27,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuning", "gfx950.json")
-KEYS = ("nodes_per_round", "lds_stack_capacity", "frontier_depth", "max_workgroups",
+KEYS = ("nodes_per_round", "lds_stack_capacity", "wg_size", "frontier_depth", "max_workgroups",
         "donate_every", "donate_min", "queue_chunk")
 
 
@@ -34,20 +35,31 @@ def size_class(n: int) -> str:
     return "small" if n <= 256 else "medium" if n <= 2048 else "large"
 
 
-def candidates(grid_full: int, large: bool = False):
-    out = []
-    rings = ((64, 1024), (64, 2048)) if large else ((16, 512), (64, 1024), (64, 2048))
-    depths = (6, 8) if large else (4, 6, 8, 10)
-    grids = (0,) if large else (0, grid_full // 2)
-    for npl, cap in rings:
-        for d in depths:
-            for wg in grids:
-                for de in (64, 128, 256):
-                    for dm in (-1, npl * 2):
-                        for qc in ((64,) if large else (32, 64)):
-                            out.append({"nodes_per_round": npl, "lds_stack_capacity": cap,
-                                        "frontier_depth": d, "max_workgroups": wg,
-                                        "donate_every": de, "donate_min": dm, "queue_chunk": qc})
+def axes(grid_full: int):
+    """The values swept per axis; (nodes per round, stack capacity) move
+    together."""
+    return [
+        ("round", [(16, 512), (64, 512), (64, 1024), (64, 2048)]),
+        ("wg_size", [64, 128, 256]),
+        ("frontier_depth", [4, 5, 6, 7, 8, 9, 10]),
+        ("max_workgroups", [0, grid_full // 2]),
+        ("donate_every", [64, 128, 256, 512]),
+        ("donate_min", [-1, 128, 256]),
+        ("queue_chunk", [16, 32, 64]),
+    ]
+
+
+def valid(cfg: dict) -> bool:
+    # several waves per workgroup need 64-node rounds
+    return cfg["wg_size"] == 64 or cfg["nodes_per_round"] == 64
+
+
+def set_axis(cfg: dict, axis: str, value) -> dict:
+    out = dict(cfg)
+    if axis == "round":
+        out["nodes_per_round"], out["lds_stack_capacity"] = value
+    else:
+        out[axis] = value
     return out
 
 
@@ -73,9 +85,11 @@ def lookup(n: int, width: int = 4, path: str = TABLE):
     return entry["best"] if entry else None
 
 
-def tune(states: np.ndarray, width: int = 4, reps: int = 2, log=print, widths=None) -> dict:
-    """Sweep the candidates on ``states`` (uint8 [n, w*w], or for a mixed
-    batch the bytes back to back with ``widths`` int32 [n])."""
+def tune(states: np.ndarray, width: int = 4, reps: int = 2, log=print, widths=None,
+         start: dict | None = None, passes: int = 2) -> dict:
+    """Coordinate descent over the axes on ``states`` (uint8 [n, w*w], or
+    for a mixed batch the bytes back to back with ``widths`` int32 [n]),
+    from ``start`` (or the library's current options)."""
     import torch
 
     from . import bpida
@@ -83,7 +97,7 @@ def tune(states: np.ndarray, width: int = 4, reps: int = 2, log=print, widths=No
     d_states = torch.from_numpy(np.ascontiguousarray(states)).cuda()
     d_len = torch.empty(n, dtype=torch.int32, device="cuda")
     d_nodes = torch.empty((n, bpida.MAX_THRESHOLDS), dtype=torch.int64, device="cuda")
-    saved = {k: bpida.get_option(k) for k in KEYS + ("mode",)}
+    saved = {k: bpida.get_option(k) for k in KEYS + ("mode", "budget_ms")}
     bpida.set_option("mode", 1)
     ref = None
     results = []
@@ -102,9 +116,17 @@ def tune(states: np.ndarray, width: int = 4, reps: int = 2, log=print, widths=No
                 raise bpida.BpidaError(rc, "autotune reference solve")
             torch.cuda.synchronize()
             t_ref = time.perf_counter() - t0
-        large = t_ref > 0.5
         grid_full = bpida.last_stats()["grid"]
-        for cfg in candidates(grid_full, large):
+        # a configuration far slower than the reference is stopped by the
+        # launch's own time budget (its workgroups exit; BPIDA_EINTERNAL)
+        bpida.set_option("budget_ms", int(max(2000.0, 8000.0 * t_ref)))
+        seen = {}
+
+        def measure(cfg):
+            nonlocal ref
+            key = tuple(cfg[k] for k in KEYS)
+            if key in seen:
+                return seen[key]
             apply(cfg)
             best = float("inf")
             for _ in range(reps + 1):  # the first call warms up / sizes the workspace
@@ -113,6 +135,15 @@ def tune(states: np.ndarray, width: int = 4, reps: int = 2, log=print, widths=No
                 rc = solve()
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t0
+                too_slow = rc == bpida.EINTERNAL and bpida.last_stats()["error_bits"] & 8
+                if rc in (bpida.ENOMEM, bpida.EINVAL) or too_slow:
+                    # a small stack on a large batch overflows the work queue,
+                    # or the configuration ran past the time budget: not
+                    # usable on this workload
+                    log("autotune %s rejected: %s" % (
+                        cfg, "time budget" if too_slow else bpida.strerror(rc)))
+                    seen[key] = float("inf")
+                    return seen[key]
                 if rc != bpida.OK:
                     raise bpida.BpidaError(rc, "autotune %r" % cfg)
                 best = min(best, dt)
@@ -125,13 +156,34 @@ def tune(states: np.ndarray, width: int = 4, reps: int = 2, log=print, widths=No
                 raise RuntimeError("configuration %r changed the results" % cfg)
             results.append(dict(cfg, seconds=round(best, 5)))
             log("autotune %s %.4f s" % (cfg, best))
+            seen[key] = best
+            return best
+
+        cur = {k: start[k] for k in KEYS} if start else None
+        if cur is None:
+            cur = {k: (saved[k] if k != "max_workgroups" else 0) for k in KEYS}
+            if cur["lds_stack_capacity"] < 0:
+                cur["lds_stack_capacity"] = 1024 if cur["nodes_per_round"] == 64 else 512
+            if cur["frontier_depth"] < 0:
+                cur["frontier_depth"] = 6
+        cur_t = measure(cur)
+        for _ in range(passes):
+            for axis, values in axes(grid_full):
+                for v in values:
+                    cfg = set_axis(cur, axis, v)
+                    if not valid(cfg) or cfg == cur:
+                        continue
+                    t = measure(cfg)
+                    if t < cur_t:
+                        cur, cur_t = cfg, t
     finally:
         for k, v in saved.items():
             bpida.set_option(k, v)
     results.sort(key=lambda r: r["seconds"])
     total = int(ref[1].view(np.uint64).sum(dtype=np.uint64))
     return {"best": {k: results[0][k] for k in KEYS}, "seconds": results[0]["seconds"],
-            "nodes": total, "n": n, "results": results}
+            "nodes": total, "n": n, "search": "coordinate descent, %d passes" % passes,
+            "results": results}
 
 
 def main():
@@ -140,6 +192,9 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="use the first n states of the workload")
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--out", default=TABLE)
+    ap.add_argument("--passes", type=int, default=2)
+    ap.add_argument("--fresh", action="store_true",
+                    help="start from the library's options, not the stored best")
     args = ap.parse_args()
     from . import instances
     widths = None
@@ -155,7 +210,11 @@ def main():
         if args.n:
             states = states[:args.n]
         n = states.shape[0]
-    res = tune(states, width, args.reps if n <= 2048 else 1, widths=widths)
+    start = lookup(n, width, args.out) if not args.fresh else None
+    if start:
+        start = dict({"wg_size": 64, "queue_chunk": 64}, **start)
+    res = tune(states, width, args.reps if n <= 2048 else 1, widths=widths, start=start,
+               passes=args.passes)
     table = {}
     if os.path.exists(args.out):
         with open(args.out) as f:
