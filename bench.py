@@ -409,12 +409,16 @@ def main():
     src_hash = kernel_source_hash()
     counters = load_traffic(src_hash, args.mode, args.workload)
     traffic = counters.get("bytes_per_launch") if counters else None
-    npl = bpida.get_option("nodes_per_round") if args.mode == "batched" else 16
+    npl = (bpida.get_option("nodes_per_round") if args.mode == "batched"
+           else bpida.get_option("plain_nodes_per_round"))
     cap = bpida.get_option("lds_stack_capacity")
     if cap < 0:
         cap = 1024 if npl == 64 else 512
-    kname = ("batch4_kernel<%d, %d>" % (cap, npl) if args.mode == "batched"
-             else "search4_kernel<%d>" % cap)
+    if args.mode == "batched":
+        kname = "batch4_kernel<%d, %d, %d>" % (cap, npl, bpida.get_option("wg_size") // 64)
+    else:
+        pn = bpida.get_option("plain_nodes_per_round")
+        kname = ("search64_kernel<%d>" if pn == 64 else "search4_kernel<%d>") % cap
     wg_total = acc.get("wg_us_search", 0) + acc.get("wg_us_queue", 0) + acc.get("wg_us_idle", 0)
 
     out = {
@@ -516,7 +520,7 @@ def main():
     if args.mode == "batched" and widths is None and not args.no_first_solution:
         out["first_solution"] = first_solution_leg(bpida, parts[0], states, width, d_states, d_len,
                                                    d_nodes, stream, not args.no_cpu_baseline)
-    probe = valu_issue_probe()
+    probe = None if args.kernel_only else valu_issue_probe()
     if probe:
         out["roofline"]["peak_measured"] = probe
         out["roofline"]["frac_of_measured"] = round(achieved / probe["gops"], 4)
