@@ -306,11 +306,15 @@ def main():
                          "legs): for profiling runs")
     ap.add_argument("--no-first-solution", action="store_true",
                     help="skip the first-solution leg (final limit stops at its first goal)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving leg (continuous batching on a Poisson request stream)")
+    ap.add_argument("--serve-n", type=int, default=4000)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.kernel_only:
-        args.no_compare = args.no_first_solution = args.no_cpu_baseline = True
+        args.no_compare = args.no_first_solution = args.no_cpu_baseline = args.no_serving = True
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
@@ -520,6 +524,18 @@ def main():
     if args.mode == "batched" and widths is None and not args.no_first_solution:
         out["first_solution"] = first_solution_leg(bpida, parts[0], states, width, d_states, d_len,
                                                    d_nodes, stream, not args.no_cpu_baseline)
+    if not args.kernel_only and not args.no_serving and widths is None and width == 4:
+        # the continuous-batching server on the c5 stream (Poisson arrivals),
+        # answers checked against the batched solve of the same states
+        from paper_1705_02843_amd import serve_bench
+        progress("serving: %d requests at %.0f per second" % (args.serve_n, args.serve_rate))
+        sv = serve_bench.serve(n=args.serve_n, rate=args.serve_rate)
+        if not sv["identical_to_batched_solve"]:
+            raise SystemExit("served answers differ from the batched solve")
+        out["serving"] = {k: sv[k] for k in ("requests", "rate_req_per_s", "p50_ms", "p90_ms",
+                                             "p99_ms", "max_ms", "instances_per_s", "nodes_per_s",
+                                             "elapsed_s", "identical_to_batched_solve",
+                                             "max_inflight")}
     probe = None if args.kernel_only else valu_issue_probe()
     if probe:
         out["roofline"]["peak_measured"] = probe

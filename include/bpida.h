@@ -205,7 +205,8 @@ int bpida_solve_device_noalloc(const uint8_t *d_states, int32_t n_instances, int
  * pinned host memory; at most `max_inflight` requests are searched at the
  * same time (each holds a device slot: split tree, counts, outputs), and a
  * request that arrives while others are on the GPU is admitted as soon as a
- * slot frees, its subtrees sharing the work queue with theirs.  Options
+ * slot frees and the queued frontier is within its budget (option
+ * admit_backlog), its subtrees sharing the work queue with theirs.  Options
  * (split depth, nodes per round, ring capacity, grid size, budget_ms) are
  * read at start.  The launch ends when the host has asked to stop and every
  * admitted request is answered, or after budget_ms.
@@ -322,6 +323,12 @@ int bpida_server_stop(void);
  *                        default).  Too small a value ships pieces of work
  *                        that cost more to move than they hold; one the stack
  *                        seldom reaches stops donation altogether.
+ *   "admit_backlog"      server: the HBM frontier budget of admission.  A
+ *                        request is admitted only while at most this many
+ *                        chunks of 64 entries wait in the work queue beyond
+ *                        the workgroups waiting for work (-1, the default:
+ *                        half the queue's slots; 0: no limit), besides the
+ *                        instance-slot budget max_inflight
  *   "push_spin"          batched mode and server: polls (of about 64 clocks
  *                        each) a push waits for a full work-queue slot before
  *                        it gives up and the pushed entries are lost (1..2^24,

@@ -478,6 +478,18 @@ __device__ void admitter_loop(const BatchArgs& A, uint64_t* st, uint16_t* sm, ui
       __builtin_amdgcn_s_sleep(32);
       continue;
     }
+    // the HBM frontier budget: while more chunks wait in the work queue than
+    // the budget allows, the searching workgroups are behind, and a new
+    // request's seeds (and later spills) could overflow it; wait
+    if (V.backlog_max > 0) {
+      int64_t backlog = 0;
+      if (lane == 0) backlog = (int64_t)(ld_relaxed(&q->tail) - ld_relaxed(&q->head));
+      backlog = (int64_t)bcast64((uint64_t)backlog);
+      if (backlog > V.backlog_max) {
+        __builtin_amdgcn_s_sleep(32);
+        continue;
+      }
+    }
     // a free instance slot (the in-flight budget); wait if none
     int slot = -1;
     for (int k0 = 0; k0 < V.slots && slot < 0; k0 += 64) {

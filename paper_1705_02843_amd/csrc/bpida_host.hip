@@ -45,6 +45,7 @@ struct Options {
   int64_t push_spin = 65536;    // batched mode: polls of a full queue slot before a push gives up
   int64_t plain_nodes_per_round = 16;  // plain mode: 16 (Alg. 1's lane map) or 64
   int64_t wg_size = 64;         // batched mode: threads per workgroup (1, 2 or 4 independent waves)
+  int64_t admit_backlog = -1;   // server: queued chunks above which admission waits (-1: half the queue, 0: none)
 };
 
 std::mutex g_mu;  // serialises solves and option changes
@@ -1073,6 +1074,7 @@ extern "C" int bpida_server_start(int32_t width, int32_t max_inflight, int32_t r
     A.srv.walks = W.d_walks + kWalkStride;
     A.srv.admitter = V.admitter.as<int32_t>();
     A.srv.in_flight = V.inflight.as<int32_t>();
+    A.srv.backlog_max = O.admit_backlog < 0 ? (int64_t)(qcap / 2) : O.admit_backlog;
     if (launch_zero_words(V.qctl.p, sizeof(QueueCtl), V.stream) != hipSuccess ||
         launch_server_setup(A, V.stream) != hipSuccess ||
         launch_batch4(cap, npl, wpg, (int)grid, A, V.stream) != hipSuccess) {
@@ -1241,6 +1243,9 @@ extern "C" int bpida_set_option(const char* key, int64_t value) {
   } else if (k == "queue_chunk") {
     if (value != 16 && value != 32 && value != 64) return BPIDA_EINVAL;
     g_opt.queue_chunk = value;
+  } else if (k == "admit_backlog") {
+    if (value < -1 || value > (int64_t(1) << 24)) return BPIDA_EINVAL;
+    g_opt.admit_backlog = value;
   } else if (k == "wg_size") {
     if (value != 64 && value != 128 && value != 256) return BPIDA_EINVAL;
     g_opt.wg_size = value;
@@ -1283,6 +1288,7 @@ extern "C" int64_t bpida_get_option(const char* key) {
   if (k == "push_spin") return g_opt.push_spin;
   if (k == "plain_nodes_per_round") return g_opt.plain_nodes_per_round;
   if (k == "wg_size") return g_opt.wg_size;
+  if (k == "admit_backlog") return g_opt.admit_backlog;
   return INT64_MIN;
 }
 

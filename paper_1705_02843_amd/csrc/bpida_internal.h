@@ -276,6 +276,9 @@ struct ServerArgs {
   const int32_t* walks; // walk counts per start cell and length, width 4
   int32_t* admitter;    // 0 until a workgroup takes the admitter role
   int32_t* in_flight;   // admitted, not yet answered
+  int64_t backlog_max;  // the HBM frontier budget: a request is admitted only
+                        // while at most this many chunks wait in the work queue
+                        // beyond the waiting workgroups (<= 0: no limit)
 };
 
 struct BatchArgs {

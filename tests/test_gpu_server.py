@@ -140,10 +140,12 @@ def test_queue_overflow_answers_enomem_never_wrong_counts(B):
     states = np.concatenate([s1, s2[pick]])
     want_len = np.concatenate([l1, l2[pick]])
     want_nodes = np.concatenate([n1, n2[pick]])
-    saved = {k: B.get_option(k) for k in ("queue_capacity", "push_spin", "max_workgroups")}
+    saved = {k: B.get_option(k) for k in ("queue_capacity", "push_spin", "max_workgroups",
+                                          "admit_backlog")}
     B.set_option("queue_capacity", 64)
     B.set_option("push_spin", 1)
     B.set_option("max_workgroups", 2)  # the admitter and one searcher
+    B.set_option("admit_backlog", 0)  # no frontier budget: admit whatever the queue holds
     got, pending = {}, {}
     try:
         with B.Server(max_inflight=64, ring_capacity=256) as srv:
@@ -178,3 +180,72 @@ def test_queue_overflow_answers_enomem_never_wrong_counts(B):
             r = srv.poll(t)
         assert srv.stop() == B.OK
     assert r is not None and r[2] == 1 and r[0] == l1[7] and (r[1] == n1[7]).all()
+
+
+def test_frontier_budget_keeps_a_small_queue_from_overflowing(B):
+    """The same burst into a small queue (256 chunks) and few workgroups, with
+    the admission's HBM frontier budget on (half the queue): requests wait to
+    be admitted instead of overflowing it, and every answer is exact."""
+    print("case: server, 256-chunk queue, 8 workgroups, frontier budget, 64 + 12 states",
+          flush=True)
+    s1, l1, n1 = load_golden("c1_walk40")
+    s2, l2, n2 = load_golden("c2_md30_38")
+    pick = [39, 77, 26, 96, 17, 44, 30, 84, 35, 36, 70, 66]
+    states = np.concatenate([s1, s2[pick]])
+    want_len = np.concatenate([l1, l2[pick]])
+    want_nodes = np.concatenate([n1, n2[pick]])
+    saved = {k: B.get_option(k) for k in ("queue_capacity", "max_workgroups", "admit_backlog")}
+    B.set_option("queue_capacity", 256)
+    B.set_option("max_workgroups", 8)
+    B.set_option("admit_backlog", -1)
+    got, pending = {}, {}
+    try:
+        with B.Server(max_inflight=64, ring_capacity=256) as srv:
+            for k in range(len(states)):
+                t = srv.submit(states[k])
+                assert t is not None
+                pending[t] = k
+            drain(srv, pending, got, time.time() + 60)
+            rc = srv.stop()
+    finally:
+        for k, v in saved.items():
+            B.set_option(k, v)
+    assert rc == B.OK, B.strerror(rc)
+    assert not pending and len(got) == len(states)
+    for k in range(len(states)):
+        ln, nodes, status = got[k]
+        assert status == 1 and ln == want_len[k] and (nodes == want_nodes[k]).all(), k
+
+
+def test_poisson_stream_of_c3_states_equals_the_oracle(B):
+    """512 states of the 4096-state uneven workload arriving as a Poisson
+    stream at 2000 requests per second (10 times the serving workload's
+    rate): every answer equals the stored oracle result for that state."""
+    print("case: server, Poisson stream of 512 c3_uneven states at 2000/s", flush=True)
+    states, want_len, want_nodes = load_golden("c3_uneven")
+    rng = np.random.default_rng(55)
+    order = rng.permutation(states.shape[0])[:512]
+    gaps = rng.exponential(1.0 / 2000.0, size=order.size)
+    arrivals = np.cumsum(gaps)
+    got, pending = {}, {}
+    with B.Server(max_inflight=256, ring_capacity=1024) as srv:
+        t0 = time.time()
+        k = 0
+        while k < order.size:
+            if time.time() - t0 >= arrivals[k]:
+                t = srv.submit(states[order[k]])
+                if t is None:
+                    time.sleep(0.0002)
+                else:
+                    pending[t] = int(order[k])
+                    k += 1
+            for tt in list(pending):
+                r = srv.poll(tt)
+                if r is not None:
+                    got[pending.pop(tt)] = r
+        drain(srv, pending, got, time.time() + 60)
+        rc = srv.stop()
+    assert rc == B.OK, B.strerror(rc)
+    assert not pending and len(got) == order.size
+    for i, (ln, nodes, status) in got.items():
+        assert status == 1 and ln == want_len[i] and (nodes == want_nodes[i]).all(), i
