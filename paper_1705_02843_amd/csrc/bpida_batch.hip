@@ -595,6 +595,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   constexpr bool kTrash = NPL == 64 && CAP >= 512 && sizeof(S) == 8;
   constexpr int kCap = kTrash ? CAP - 1 : CAP;
   const LaneMap M = make_lane_map(lane);
+  const RoundConsts4 rk = make_round_consts4();
   // Donating from a shallow stack hands over pieces too small to pay for the
   // transfer; a threshold the stack seldom reaches stops donation and leaves
   // subtrees on one workgroup.  Default: four rounds' worth of pops, at most
@@ -685,7 +686,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
     if constexpr (NPL == 16) {
       top = bp_round<CAP>((uint64_t*)st, sm, top, kp, limit, M, goals, fmin);
     } else {
-      top = bp_round64w<W, CAP, kTrash>(st, sm, top, kp, goals);
+      top = bp_round64w<W, CAP, kTrash, false>(st, sm, top, kp, goals, rk);
     }
     // the spill above keeps every round inside the stack; a round that ended
     // past it would have overwritten entries (reported, never silent)
@@ -702,6 +703,22 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
       }
       if (poll && (tick & 63u) == 0 && wave_bcast(lane == 0 ? ld_relaxed(&A.is[inst].stop) : 0))
         break;
+    }
+    if constexpr (NPL == 64 && !FS) {
+      // Full rounds with nothing else to test: while the stack holds 64
+      // entries and has room for their children (the condition under which
+      // the round above needs no spill) and no poll is due, 64-node rounds
+      // run back to back; their counts are added once at the end.  (The
+      // first-solution search keeps its per-round goal test above.)
+      const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane((int)(poll_mask - (tick & poll_mask)));
+      uint32_t r = 0;
+      while (r < n && top - 64u <= (uint32_t)(kCap - kGrow - 64)) {
+        top = bp_round64w<W, CAP, kTrash, true>(st, sm, top, 64, goals, rk);
+        ++r;
+      }
+      tick += r;
+      expanded += 64ull * r;
+      wc.rounds += r;
     }
   }
   // 64-node rounds: a pruned child always has f = limit + 2 (bp_round64w),

@@ -206,21 +206,83 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v) {
   return v;
 }
 
+// The same for a 64-bit value; also a way to keep a constant in vector
+// registers (as the operand of a 64-bit compare or shift it would be
+// reloaded into scalar registers every round).
+__device__ __forceinline__ uint64_t opaque64(uint64_t v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
+// Constants of the width-4 round, held in vector registers for a whole unit:
+// the four moves' up tables (bit "index" is Board<4>::up for that index),
+// the goal and the legal-move table.  Set once before the rounds instead of
+// once per round.
+struct RoundConsts4 {
+  uint32_t up[4];
+  uint64_t goal;
+  uint64_t legal;
+};
+
+// Move A's up table as Board<4>::up reads it: the table shifted by the
+// neighbour's offset, transposed for columns.
+template <int A>
+constexpr uint32_t up_table4() {
+  using B = Board<4>;
+  constexpr bool vert = A == 0 || A == 3;
+  constexpr int step = (A == 0 || A == 1) ? -1 : 1;
+  constexpr uint32_t tab = vert ? B::table(A) : B::transposed(B::table(A));
+  constexpr uint32_t sh = vert ? 1u : 4u;
+  return step < 0 ? (tab << sh) : (tab >> sh);
+}
+
+// Compile-time proof: the round's lookup in these tables gives Board<4>::up
+// for every blank cell, move and tile.
+template <int A>
+constexpr bool check_up_table4() {
+  using B = Board<4>;
+  constexpr bool vert = A == 0 || A == 3;
+  for (uint32_t b = 0; b < 16; ++b)
+    for (uint32_t t = 0; t < 16; ++t) {
+      const uint32_t rp = B::row_part(b), cp = B::col_part(b);
+      const uint32_t idx = vert ? ((t & 12u) | rp) : ((t & 3u) | cp);
+      if (((up_table4<A>() >> idx) & 1u) != B::template up<A>(t, rp, cp)) return false;
+    }
+  return true;
+}
+static_assert(check_up_table4<0>() && check_up_table4<1>() && check_up_table4<2>() &&
+                  check_up_table4<3>(),
+              "width-4 up tables disagree with Board::up");
+
+__device__ __forceinline__ RoundConsts4 make_round_consts4() {
+  RoundConsts4 k;
+  k.up[0] = opaque(up_table4<0>());
+  k.up[1] = opaque(up_table4<1>());
+  k.up[2] = opaque(up_table4<2>());
+  k.up[3] = opaque(up_table4<3>());
+  k.goal = opaque64(Board<4>::goal());
+  k.legal = opaque64(legal_table<4>());
+  return k;
+}
+
 // Per-node values shared by the four moves of a 64-node round.
 struct NodeCtx {
   uint32_t b;      // blank cell
-  uint32_t shb;    // BITS * b
+  uint32_t shb;    // BITS * b (width 4: in the low six bits only)
   uint32_t rowi;   // vertical moves: the blank's row (table index part)
   uint32_t coli;   // horizontal moves: the blank's column (x W for width 4)
   uint32_t lmx;    // bit (A + 4 up): move A survives the f test
   uint32_t mbase;  // slack << 8 | blank
   uint32_t trash;  // byte offset of the spare entry (branch-free stores)
+  uint32_t sr_lo;  // width 4: low word of s >> 4b (the cells after the blank)
+  uint32_t su_hi;  // width 4: high word of s << (63 - 4b) (the cells before it)
 };
 
 // One move for every lane of a 64-node round (see bp_round64w).
 template <int W, int CAP, int A, bool TRASH>
 __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm, uint32_t& out,
-                                          const typename Board<W>::S s, const NodeCtx& c) {
+                                          const typename Board<W>::S s, const NodeCtx& c,
+                                          const RoundConsts4& rk) {
   using B = Board<W>;
   using S = typename B::S;
   constexpr int delta = A == 0 ? -W : A == 1 ? -1 : A == 2 ? 1 : W;
@@ -229,9 +291,24 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
   // shift to the neighbour's cell; it wraps (and the tile is unused) when
   // the move is illegal, and needs no mask on a legal one
   const uint32_t shu = c.shb + (uint32_t)(B::BITS * delta);
-  const uint32_t sh_n = shu & (8u * sizeof(S) - 1u);
-  const uint32_t x = (uint32_t)(s >> sh_n);  // tile t in the low BITS bits
-  const uint32_t up = B::template up<A>(x, c.rowi, c.coli);
+  uint32_t tile;  // the neighbour's tile t
+  uint32_t up;    // 1 iff the move takes t away from its goal cell
+  if constexpr (W == 4) {
+    // cell b + d sits at bits 4d of s >> 4b (d > 0), and at bits 63 + 4d - 32
+    // of the high word of s << (63 - 4b) (d < 0): one extract gives the tile
+    // alone, for the table index and for the successor
+    uint32_t x;
+    if constexpr (A == 0) x = (c.su_hi >> 15) & 15u;
+    else if constexpr (A == 1) x = (c.su_hi >> 27) & 15u;
+    else if constexpr (A == 2) x = (c.sr_lo >> 4) & 15u;
+    else x = (c.sr_lo >> 16) & 15u;
+    tile = opaque(x);
+    up = (rk.up[A] >> (vert ? (tile & 12u) | c.rowi : (tile & 3u) | c.coli)) & 1u;
+  } else {
+    const uint32_t x = (uint32_t)(s >> (shu & (8u * sizeof(S) - 1u)));
+    tile = x & B::MASK;
+    up = B::template up<A>(x, c.rowi, c.coli);
+  }
   const uint32_t kb = opaque((c.lmx >> (A + 4 * up)) & 1u);
   const uint64_t km = __builtin_amdgcn_uicmp(kb, 0u, 33);  // lanes with kb != 0
   // TRASH: every lane builds its child (a vector instruction costs the same
@@ -244,13 +321,13 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
     if constexpr (A >= 2 && sizeof(S) == 8) {
       // the subtraction as the addition of -K t sign-extended to 64 bits:
       // one 64-bit add instead of a subtract with borrow
-      const uint32_t nkt = mul_i24(-(int)K, x & B::MASK);
-      cs = s + (((0xFFFFFFFFull << 32) | nkt) << c.shb);
+      const uint32_t nkt = mul_i24(-(int)K, tile);
+      cs = s + (((0xFFFFFFFFull << 32) | nkt) << (c.shb & 63u));
     } else {
       uint32_t kt;
-      if constexpr (K < (1u << 24)) kt = mul_u24(K, x & B::MASK);
-      else kt = K * (x & B::MASK);  // 5x5 rows: K = 2^25 - 1
-      const S d = (S)kt << (A < 2 ? shu : c.shb);
+      if constexpr (K < (1u << 24)) kt = mul_u24(K, tile);
+      else kt = K * tile;  // 5x5 rows: K = 2^25 - 1
+      const S d = (S)kt << ((A < 2 ? shu : c.shb) & (8u * sizeof(S) - 1u));
       cs = A < 2 ? s + d : s - d;
     }
     // stack meta: n | (3 - A) << 5 | (slack - 2 up) << 8
@@ -272,14 +349,14 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
 // kp = min(64, top) nodes from a stack of entries [0, top), tests them for
 // the goal and pushes every legal, non-undoing child with f <= limit.  The
 // caller guarantees top + 3*kp <= CAP (CAP - 1 with TRASH, whose stores of
-// dropped children go to entry CAP - 1; no position wraps).  The
-// round does not track the f of pruned children: every slack on the stack is
-// even (f keeps the parity of h0, and so does the limit), so a child is
-// pruned only from slack 0, moving a tile away from its goal, and its f is
-// the limit + 2.
-template <int W, int CAP, bool TRASH>
+// dropped children go to entry CAP - 1; no position wraps); FULL: it also
+// guarantees kp = 64, so no lane is idle.  The round does not track the f
+// of pruned children: every slack on the stack is even (f keeps the parity
+// of h0, and so does the limit), so a child is pruned only from slack 0,
+// moving a tile away from its goal, and its f is the limit + 2.
+template <int W, int CAP, bool TRASH, bool FULL>
 __device__ __forceinline__ uint32_t bp_round64w(typename Board<W>::S* st, uint16_t* sm, uint32_t top, int kp,
-                                           int& goals) {
+                                           int& goals, const RoundConsts4& rk) {
   using B = Board<W>;
   using S = typename B::S;
   const int lane = lane_id();
@@ -288,35 +365,43 @@ __device__ __forceinline__ uint32_t bp_round64w(typename Board<W>::S* st, uint16
   const uint32_t pst = (base + (uint32_t)lane) << LS;
   const S s = *(const S*)((const char*)st + pst);
   const uint32_t m = *(const uint16_t*)((const char*)sm + (pst >> (LS - 1)));
-  const uint64_t actm = kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
+  const uint64_t actm = FULL || kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
   uint64_t gm;
-  if constexpr (sizeof(S) == 8) gm = __builtin_amdgcn_uicmpl((uint64_t)s, (uint64_t)B::goal(), 32);
+  if constexpr (W == 4) gm = __builtin_amdgcn_uicmpl((uint64_t)s, rk.goal, 32);
+  else if constexpr (sizeof(S) == 8) gm = __builtin_amdgcn_uicmpl((uint64_t)s, (uint64_t)B::goal(), 32);
   else gm = __builtin_amdgcn_ballot_w64(s == B::goal());
   goals += __popcll(gm & actm);
   NodeCtx c;
   c.b = m & 31u;
-  c.shb = opaque(B::BITS * c.b);
   const uint32_t fb = (m >> 5) & 7u;
   uint32_t lm;
-  if constexpr (W * W <= 16) {
-    lm = (uint32_t)(legal_table<W>() >> (4u * c.b)) & ~(1u << fb) & 15u;
+  if constexpr (W == 4) {
+    // m << 2 has 4b in its low six bits, all that a 64-bit shift reads
+    c.shb = opaque(m << 2);
+    c.sr_lo = (uint32_t)(s >> (c.shb & 63u));
+    c.su_hi = (uint32_t)((s << (~c.shb & 63u)) >> 32);
+    lm = (uint32_t)(rk.legal >> (c.shb & 63u)) & ~(1u << fb) & 15u;
+    c.coli = c.shb & 12u;
   } else {
-    lm = B::legal(c.b) & ~(1u << fb);
+    c.shb = opaque(B::BITS * c.b);
+    if constexpr (W * W <= 16) lm = (uint32_t)(legal_table<W>() >> (4u * c.b)) & ~(1u << fb) & 15u;
+    else lm = B::legal(c.b) & ~(1u << fb);
+    c.coli = B::col_part(c.b);
   }
+  c.rowi = B::row_part(c.b);
   // moves that survive: any legal one if its tile approaches its goal, and
   // only with slack >= 2 if it moves away (bits 0..3 and 4..7 of lm * 17);
   // lanes past kp keep nothing
   const bool roomy = m >= (2u << 8);
-  c.lmx = mul_u24(lm, sel_lanes(actm, roomy ? 17u : 1u));
-  c.rowi = B::row_part(c.b);
-  c.coli = B::col_part(c.b);
+  if constexpr (FULL) c.lmx = mul_u24(lm, roomy ? 17u : 1u);
+  else c.lmx = mul_u24(lm, sel_lanes(actm, roomy ? 17u : 1u));
   c.mbase = (m & 0xFF00u) | c.b;
   c.trash = (uint32_t)(CAP - 1) << LS;
   uint32_t out = base;
-  bp_move_w<W, CAP, 0, TRASH>(st, sm, out, s, c);
-  bp_move_w<W, CAP, 1, TRASH>(st, sm, out, s, c);
-  bp_move_w<W, CAP, 2, TRASH>(st, sm, out, s, c);
-  bp_move_w<W, CAP, 3, TRASH>(st, sm, out, s, c);
+  bp_move_w<W, CAP, 0, TRASH>(st, sm, out, s, c, rk);
+  bp_move_w<W, CAP, 1, TRASH>(st, sm, out, s, c, rk);
+  bp_move_w<W, CAP, 2, TRASH>(st, sm, out, s, c, rk);
+  bp_move_w<W, CAP, 3, TRASH>(st, sm, out, s, c, rk);
   WAVE_SYNC();
   return out;
 }

@@ -339,6 +339,7 @@ __global__ __launch_bounds__(64) void search64_kernel(const Node* __restrict__ r
   int err = 0;
   int spill_hw = 0;
 
+  const RoundConsts4 rk = make_round_consts4();
   bool stopped = false;
   for (;;) {
     if (stop && wave_bcast(lane == 0 ? __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0))
@@ -396,7 +397,7 @@ __global__ __launch_bounds__(64) void search64_kernel(const Node* __restrict__ r
         top -= 64u;
       }
       const int kp = (int)min(top, 64u);
-      top = bp_round64w<4, CAP, true>(st, sm, top, kp, goals);
+      top = bp_round64w<4, CAP, true, false>(st, sm, top, kp, goals, rk);
       expanded += (uint64_t)kp;
       rounds += 1;
       if (stop) {
