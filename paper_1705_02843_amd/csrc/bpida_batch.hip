@@ -582,13 +582,16 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
                          uint16_t* sm, int cnt, WgCounters& wc, uint32_t& tick, uint64_t deadline,
                          uint64_t& expanded, int& goals, int& fmin) {
   static_assert(NPL == 64 || W == 4, "16-node rounds are the 4x4 map");
-  static_assert((CAP & (CAP - 1)) == 0 && CAP >= (NPL == 64 ? 256 : 128), "stack size");
+  static_assert(NPL == 64 ? CAP >= 256 : ((CAP & (CAP - 1)) == 0 && CAP >= 128), "stack size");
   using S = typename Board<W>::S;
   const int lane = lane_id();
   QueueCtl* q = A.q;
   const bool wide = W == 5;
-  // largest growth of one round: a popped node has at most 4 children
-  constexpr int kGrow = NPL == 16 ? 32 : 3 * 64;
+  // largest growth of one round: a node has at most 3 children (its parent's
+  // cell is excluded).  Only a root of the split (depth 0) has no parent and
+  // may have 4, and a root is expanded in the unit's first round, which
+  // starts from one chunk (at most 64 entries) and so cannot overflow.
+  constexpr int kGrow = NPL == 16 ? 32 : 2 * 64;
   // 64-node rounds on 3x3 and 4x4 stacks of 512+ entries store without
   // branches: a lane that keeps no child writes it to the last entry, which
   // never holds the stack
@@ -661,9 +664,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
     }
     if (avail + kGrow > kCap) {
       // LDS could overflow: move the oldest entries to the queue, 64 at a
-      // time, until the largest round fits.  One chunk is not always enough:
-      // a 64-node round can add up to 128 entries (three children a node),
-      // more than one chunk takes away.
+      // time, until the largest round fits.
       do {
         const S t = st[lane];
         const uint16_t m = sm[lane];
@@ -712,10 +713,14 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
       // first-solution search keeps its per-round goal test above.)
       const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane((int)(poll_mask - (tick & poll_mask)));
       uint32_t r = 0;
-      while (r < n && top - 64u <= (uint32_t)(kCap - kGrow - 64)) {
-        top = bp_round64w<W, CAP, kTrash, true>(st, sm, top, 64, goals, rk);
+      uint64_t gm = 0;  // lanes that expanded a goal (only "any" matters)
+      for (;;) {
+        if (r >= n) break;
+        if (top - 64u > (uint32_t)(kCap - kGrow - 64)) break;
+        top = bp_round64w<W, CAP, kTrash, true>(st, sm, top, 64, gm, rk);
         ++r;
       }
+      if (gm != 0) goals += 1;
       tick += r;
       expanded += 64ull * r;
       wc.rounds += r;
@@ -735,9 +740,19 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
 // 10*CAP-byte stack, CAP entries of u64 tiles + u16 meta for widths 3 and 4,
 // CAP/2 entries of 128-bit tiles + u16 meta for width 5; the width is read
 // per chunk from the instance.
+//
+// Waves per SIMD a one-wave workgroup's stack allows (LDS: 160 KB per
+// compute unit, 10 bytes an entry): 16 at 1024 entries, 20 at 768, 24 at
+// 640.  The launch bound keeps the vector registers within that occupancy
+// (at most 96 and 80 per lane).
+template <int CAP, int NPL>
+constexpr int batch_waves_per_simd() {
+  return NPL != 64 ? 1 : CAP <= 640 ? 6 : CAP <= 768 ? 5 : 1;
+}
+
 template <int CAP, int NPL, int WPG>
-__global__ __launch_bounds__(64 * WPG) void batch4_kernel(BatchArgs A) {
-  static_assert((CAP & (CAP - 1)) == 0 && CAP >= 128, "stack size");
+__global__ __launch_bounds__(64 * WPG, (batch_waves_per_simd<CAP, NPL>())) void batch4_kernel(BatchArgs A) {
+  static_assert(CAP % 16 == 0 && (NPL == 64 || (CAP & (CAP - 1)) == 0), "stack size");
   static_assert(NPL == 16 || NPL == 64, "nodes per round");
   static_assert(NPL == 16 || CAP >= 256, "stack too small for 64-node rounds");
   static_assert(WPG == 1 || WPG == 2 || WPG == 4, "waves per workgroup");
@@ -1178,7 +1193,7 @@ static int occupancy_t() {
 // Supported (stack capacity, nodes per round, waves per workgroup) triples.
 #define BATCH_CONFIGS(X)                                                                         \
   X(128, 16, 1) X(256, 16, 1) X(512, 16, 1) X(1024, 16, 1) X(2048, 16, 1) X(256, 64, 1)          \
-  X(512, 64, 1) X(1024, 64, 1) X(2048, 64, 1) X(512, 64, 2) X(1024, 64, 2) X(2048, 64, 2)        \
+  X(512, 64, 1) X(640, 64, 1) X(768, 64, 1) X(1024, 64, 1) X(2048, 64, 1) X(512, 64, 2) X(1024, 64, 2) X(2048, 64, 2)        \
   X(512, 64, 4) X(1024, 64, 4) X(2048, 64, 4)
 
 hipError_t launch_batch4(int lds_cap, int npl, int wpg, int grid, const BatchArgs& A, hipStream_t s) {

@@ -350,19 +350,20 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
 // the goal and pushes every legal, non-undoing child with f <= limit.  The
 // caller guarantees top + 3*kp <= CAP (CAP - 1 with TRASH, whose stores of
 // dropped children go to entry CAP - 1; no position wraps); FULL: it also
-// guarantees kp = 64, so no lane is idle.  The round does not track the f
+// guarantees kp = 64, so no lane is idle, and passes a 64-bit mask that
+// collects the lanes that expanded a goal.  The round does not track the f
 // of pruned children: every slack on the stack is even (f keeps the parity
 // of h0, and so does the limit), so a child is pruned only from slack 0,
 // moving a tile away from its goal, and its f is the limit + 2.
-template <int W, int CAP, bool TRASH, bool FULL>
+template <int W, int CAP, bool TRASH, bool FULL, typename G>
 __device__ __forceinline__ uint32_t bp_round64w(typename Board<W>::S* st, uint16_t* sm, uint32_t top, int kp,
-                                           int& goals, const RoundConsts4& rk) {
+                                           G& goals, const RoundConsts4& rk) {
   using B = Board<W>;
   using S = typename B::S;
   const int lane = lane_id();
   const uint32_t base = top - (uint32_t)kp;
   constexpr uint32_t LS = sizeof(S) == 8 ? 3 : 4;
-  const uint32_t pst = (base + (uint32_t)lane) << LS;
+  const uint32_t pst = opaque((base + (uint32_t)lane) << LS);
   const S s = *(const S*)((const char*)st + pst);
   const uint32_t m = *(const uint16_t*)((const char*)sm + (pst >> (LS - 1)));
   const uint64_t actm = FULL || kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
@@ -370,7 +371,9 @@ __device__ __forceinline__ uint32_t bp_round64w(typename Board<W>::S* st, uint16
   if constexpr (W == 4) gm = __builtin_amdgcn_uicmpl((uint64_t)s, rk.goal, 32);
   else if constexpr (sizeof(S) == 8) gm = __builtin_amdgcn_uicmpl((uint64_t)s, (uint64_t)B::goal(), 32);
   else gm = __builtin_amdgcn_ballot_w64(s == B::goal());
-  goals += __popcll(gm & actm);
+  // goals: a count (int), or (FULL) the union of the rounds' goal masks
+  if constexpr (FULL) goals |= gm;
+  else goals += __popcll(gm & actm);
   NodeCtx c;
   c.b = m & 31u;
   const uint32_t fb = (m >> 5) & 7u;

@@ -327,7 +327,9 @@ __global__ __launch_bounds__(64) void search64_kernel(const Node* __restrict__ r
   __shared__ __attribute__((aligned(16))) uint64_t st[CAP];
   __shared__ uint16_t sm[CAP];
   constexpr uint32_t kCap = CAP - 1;
-  constexpr uint32_t kGrow = 3 * 64;
+  // largest growth of one round: at most 3 children a node (a unit starts
+  // from one root, whose round cannot overflow)
+  constexpr uint32_t kGrow = 2 * 64;
 
   const int lane = threadIdx.x;
   uint64_t* sp_t = spill_tiles + (size_t)blockIdx.x * spill_cap;

@@ -124,7 +124,7 @@ def test_split_depths_agree(opts, depth, mode):
 
 CAPS = [("plain", 128), ("plain", 1024), ("plain64", 512), ("plain64", 2048),
         ("batched16", 128), ("batched16", 256), ("batched16", 2048), ("batched", 512),
-        ("batched", 1024), ("batched", 2048)]
+        ("batched", 640), ("batched", 768), ("batched", 1024), ("batched", 2048)]
 
 
 @pytest.mark.parametrize("mode,cap", CAPS)
