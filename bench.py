@@ -464,9 +464,10 @@ def main():
                      "launches_per_step": launches // max(1, args.steps),
                      "search_nodes_per_s_in_kernel": round(search_nodes / (search_us * 1e-6), 1)
                      if search_us else None},
-        "counters": ({k: counters[k] for k in ("valu_busy_frac", "active_lanes_frac",
-                                                "valu_instructions_per_node",
-                                                "lds_bank_conflict_cycles", "waves_per_simd")
+        "counters": ({k: counters[k] for k in ("instructions_per_round", "salu_instructions_per_round",
+                                                "valu_instructions_per_node", "valu_per_cu_clock",
+                                                "active_lanes_frac", "lds_bank_conflict_cycles",
+                                                "waves_per_simd")
                       if k in counters} if counters else None),
         "search_rounds_per_step": rounds // max(1, args.steps),
         "pop_occupancy": round(search_nodes / (float(npl) * rounds), 4) if rounds else None,

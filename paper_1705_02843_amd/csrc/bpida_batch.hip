@@ -592,11 +592,10 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   // may have 4, and a root is expanded in the unit's first round, which
   // starts from one chunk (at most 64 entries) and so cannot overflow.
   constexpr int kGrow = NPL == 16 ? 32 : 2 * 64;
-  // 64-node rounds on 3x3 and 4x4 stacks of 512+ entries store without
-  // branches: a lane that keeps no child writes it to the last entry, which
-  // never holds the stack
-  constexpr bool kTrash = NPL == 64 && CAP >= 512 && sizeof(S) == 8;
-  constexpr int kCap = kTrash ? CAP - 1 : CAP;
+  // 64-node rounds on 3x3 and 4x4 stacks store without branches (under the
+  // keep mask)
+  constexpr bool kMasked = NPL == 64 && sizeof(S) == 8;
+  constexpr int kCap = CAP;
   const LaneMap M = make_lane_map(lane);
   const RoundConsts4 rk = make_round_consts4();
   // Donating from a shallow stack hands over pieces too small to pay for the
@@ -687,7 +686,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
     if constexpr (NPL == 16) {
       top = bp_round<CAP>((uint64_t*)st, sm, top, kp, limit, M, goals, fmin);
     } else {
-      top = bp_round64w<W, CAP, kTrash, false>(st, sm, top, kp, goals, rk);
+      top = bp_round64w<W, CAP, kMasked, false>(st, sm, top, kp, goals, rk);
     }
     // the spill above keeps every round inside the stack; a round that ended
     // past it would have overwritten entries (reported, never silent)
@@ -717,7 +716,7 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
       for (;;) {
         if (r >= n) break;
         if (top - 64u > (uint32_t)(kCap - kGrow - 64)) break;
-        top = bp_round64w<W, CAP, kTrash, true>(st, sm, top, 64, gm, rk);
+        top = bp_round64w<W, CAP, kMasked, true>(st, sm, top, 64, gm, rk);
         ++r;
       }
       if (gm != 0) goals += 1;

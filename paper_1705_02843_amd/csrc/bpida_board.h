@@ -191,13 +191,6 @@ __device__ __forceinline__ uint32_t sel_lanes(uint64_t lm, uint32_t v) {
   return r;
 }
 
-// a where the lane's bit of m is set, else b (m read from scalar registers)
-__device__ __forceinline__ uint32_t sel_mask(uint64_t m, uint32_t a, uint32_t b) {
-  uint32_t r;
-  asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(m));
-  return r;
-}
-
 // Hides a value's known bits from the optimiser (no instruction is emitted).
 // Used where the compiler would otherwise re-derive one condition in two
 // forms, or keep a shift-amount mask the hardware applies anyway.
@@ -265,6 +258,11 @@ __device__ __forceinline__ RoundConsts4 make_round_consts4() {
   return k;
 }
 
+// Byte address of an LDS object (its offset in the workgroup's LDS).
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
 // Per-node values shared by the four moves of a 64-node round.
 struct NodeCtx {
   uint32_t b;      // blank cell
@@ -273,13 +271,12 @@ struct NodeCtx {
   uint32_t coli;   // horizontal moves: the blank's column (x W for width 4)
   uint32_t lmx;    // bit (A + 4 up): move A survives the f test
   uint32_t mbase;  // slack << 8 | blank
-  uint32_t trash;  // byte offset of the spare entry (branch-free stores)
   uint32_t sr_lo;  // width 4: low word of s >> 4b (the cells after the blank)
   uint32_t su_hi;  // width 4: high word of s << (63 - 4b) (the cells before it)
 };
 
 // One move for every lane of a 64-node round (see bp_round64w).
-template <int W, int CAP, int A, bool TRASH>
+template <int W, int CAP, int A, bool MASKED>
 __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm, uint32_t& out,
                                           const typename Board<W>::S s, const NodeCtx& c,
                                           const RoundConsts4& rk) {
@@ -311,10 +308,12 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
   }
   const uint32_t kb = opaque((c.lmx >> (A + 4 * up)) & 1u);
   const uint64_t km = __builtin_amdgcn_uicmp(kb, 0u, 33);  // lanes with kb != 0
-  // TRASH: every lane builds its child (a vector instruction costs the same
-  // for any number of active lanes) and the lanes that keep none store it to
-  // the spare entry, so the move needs no branch
-  if (TRASH || kb != 0u) {
+  // MASKED (64-bit states): every lane builds its child (a vector
+  // instruction costs the same for any number of active lanes) and only the
+  // lanes that keep it store, under the mask; no branch.  Otherwise (5x5)
+  // the child is built in a branch that the compiler skips when no lane
+  // keeps the move.
+  if (MASKED || kb != 0u) {
     // successor: t moves from n to b, i.e. the packed word changes by
     // t * (base^b - base^n) = +/- (K * t) << (BITS * min(b, n))
     S cs;
@@ -337,10 +336,27 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
     // byte offsets into the stack: entry out + r (below CAP: the caller
     // leaves room for the largest round)
     constexpr uint32_t LS = sizeof(S) == 8 ? 3 : 4;
-    uint32_t pst = (r + out) << LS;
-    if constexpr (TRASH) pst = sel_mask(km, pst, c.trash);
-    *(S*)((char*)st + pst) = cs;
-    *(uint16_t*)((char*)sm + (pst >> (LS - 1))) = (uint16_t)cm;
+    const uint32_t pst = (r + out) << LS;
+    if constexpr (MASKED) {
+      // the two stores under the keep mask, with no branch around them (the
+      // meta array follows the CAP tiles: sm == st + CAP).  The compiler
+      // would put a skip jump around stores in a divergent branch; this asm
+      // sets EXEC to the mask, stores and restores EXEC itself.
+      const uint32_t as = lds_addr(st) + pst;
+      const uint32_t am = lds_addr(st) + (pst >> (LS - 1));
+      uint64_t saved;
+      asm volatile(
+          "s_and_saveexec_b64 %0, %1\n\t"
+          "ds_write_b64 %2, %3\n\t"
+          "ds_write_b16 %4, %5 offset:%6\n\t"
+          "s_mov_b64 exec, %0"
+          : "=&s"(saved)
+          : "s"(km), "v"(as), "v"(cs), "v"(am), "v"(cm), "i"(CAP * (int)sizeof(S))
+          : "memory", "scc");
+    } else {
+      *(S*)((char*)st + pst) = cs;
+      *(uint16_t*)((char*)sm + (pst >> (LS - 1))) = (uint16_t)cm;
+    }
   }
   out += (uint32_t)__popcll(km);
 }
@@ -348,14 +364,15 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
 // One BPDFS round with one popped node per lane, for any board width: pops
 // kp = min(64, top) nodes from a stack of entries [0, top), tests them for
 // the goal and pushes every legal, non-undoing child with f <= limit.  The
-// caller guarantees top + 3*kp <= CAP (CAP - 1 with TRASH, whose stores of
-// dropped children go to entry CAP - 1; no position wraps); FULL: it also
+// caller guarantees that the children fit, top + 2*kp <= CAP (three
+// children a node at most; only a root, expanded in a unit's first round
+// from at most 64 entries, can have four; no position wraps); FULL: it also
 // guarantees kp = 64, so no lane is idle, and passes a 64-bit mask that
 // collects the lanes that expanded a goal.  The round does not track the f
 // of pruned children: every slack on the stack is even (f keeps the parity
 // of h0, and so does the limit), so a child is pruned only from slack 0,
 // moving a tile away from its goal, and its f is the limit + 2.
-template <int W, int CAP, bool TRASH, bool FULL, typename G>
+template <int W, int CAP, bool MASKED, bool FULL, typename G>
 __device__ __forceinline__ uint32_t bp_round64w(typename Board<W>::S* st, uint16_t* sm, uint32_t top, int kp,
                                            G& goals, const RoundConsts4& rk) {
   using B = Board<W>;
@@ -399,12 +416,11 @@ __device__ __forceinline__ uint32_t bp_round64w(typename Board<W>::S* st, uint16
   if constexpr (FULL) c.lmx = mul_u24(lm, roomy ? 17u : 1u);
   else c.lmx = mul_u24(lm, sel_lanes(actm, roomy ? 17u : 1u));
   c.mbase = (m & 0xFF00u) | c.b;
-  c.trash = (uint32_t)(CAP - 1) << LS;
   uint32_t out = base;
-  bp_move_w<W, CAP, 0, TRASH>(st, sm, out, s, c, rk);
-  bp_move_w<W, CAP, 1, TRASH>(st, sm, out, s, c, rk);
-  bp_move_w<W, CAP, 2, TRASH>(st, sm, out, s, c, rk);
-  bp_move_w<W, CAP, 3, TRASH>(st, sm, out, s, c, rk);
+  bp_move_w<W, CAP, 0, MASKED>(st, sm, out, s, c, rk);
+  bp_move_w<W, CAP, 1, MASKED>(st, sm, out, s, c, rk);
+  bp_move_w<W, CAP, 2, MASKED>(st, sm, out, s, c, rk);
+  bp_move_w<W, CAP, 3, MASKED>(st, sm, out, s, c, rk);
   WAVE_SYNC();
   return out;
 }

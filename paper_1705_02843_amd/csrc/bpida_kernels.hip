@@ -310,11 +310,11 @@ __global__ __launch_bounds__(64) void search4_kernel(const Node* __restrict__ ro
 // search64: as search4 (persistent grid, roots through the cursor, HBM spill
 // stack per workgroup, first-solution stop flag, per-root round counts for
 // the static load balancing), with 64-node rounds on a linear LDS stack
-// [0, top).  Entry CAP - 1 takes the children a round drops (its stores are
-// branch-free), so the stack proper ends at CAP - 1.  The oldest 64 entries
-// go to the spill stack when the largest round (192 new entries: a start
-// node has four children) might not fit; when fewer than 64 entries remain,
-// the last spilled chunk comes back below them.
+// [0, top) (the round's stores are branch-free, under the keep mask).  The
+// oldest 64 entries go to the spill stack when the largest round (128 new
+// entries: three children a node; the start node, alone in the first round,
+// may have four) might not fit; when fewer than 64 entries remain, the last
+// spilled chunk comes back below them.
 template <int CAP>
 __global__ __launch_bounds__(64) void search64_kernel(const Node* __restrict__ roots, int nroots,
                                                       int limit, int32_t* __restrict__ cursor,
@@ -324,9 +324,12 @@ __global__ __launch_bounds__(64) void search64_kernel(const Node* __restrict__ r
                                                       int32_t* __restrict__ stop,
                                                       uint32_t* __restrict__ load) {
   static_assert((CAP & (CAP - 1)) == 0 && CAP >= 512, "stack size for 64-node rounds");
-  __shared__ __attribute__((aligned(16))) uint64_t st[CAP];
-  __shared__ uint16_t sm[CAP];
-  constexpr uint32_t kCap = CAP - 1;
+  // one array: CAP tiles, then CAP meta words (the layout the batched
+  // kernel's stacks have, sm == st + CAP)
+  __shared__ __attribute__((aligned(16))) uint64_t lds[(10 * CAP) / 8];
+  uint64_t* st = lds;
+  uint16_t* sm = (uint16_t*)(lds + CAP);
+  constexpr uint32_t kCap = CAP;
   // largest growth of one round: at most 3 children a node (a unit starts
   // from one root, whose round cannot overflow)
   constexpr uint32_t kGrow = 2 * 64;
@@ -402,7 +405,20 @@ __global__ __launch_bounds__(64) void search64_kernel(const Node* __restrict__ r
       top = bp_round64w<4, CAP, true, false>(st, sm, top, kp, goals, rk);
       expanded += (uint64_t)kp;
       rounds += 1;
-      if (stop) {
+      if (!stop) {
+        // all-solutions search: full rounds back to back while the stack
+        // holds 64 entries and has room for their children (no spill or
+        // refill due); counts are added once at the end
+        uint64_t gm = 0;  // lanes that expanded a goal (only "any" matters)
+        uint32_t n = 0;
+        while (top - 64u <= kCap - kGrow - 64u) {
+          top = bp_round64w<4, CAP, true, true>(st, sm, top, 64, gm, rk);
+          ++n;
+        }
+        if (gm != 0) goals += 1;
+        expanded += 64ull * n;
+        rounds += n;
+      } else {
         if (goals > 0) {
           if (lane == 0) __hip_atomic_store(stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           stopped = true;
