@@ -466,6 +466,7 @@ def main():
                      if search_us else None},
         "counters": ({k: counters[k] for k in ("instructions_per_round", "salu_instructions_per_round",
                                                 "valu_instructions_per_node", "valu_per_cu_clock",
+                                                "valu_issue_frac",
                                                 "active_lanes_frac", "lds_bank_conflict_cycles",
                                                 "waves_per_simd")
                       if k in counters} if counters else None),
