@@ -311,20 +311,22 @@ def test_lost_work_fails_fast(opts):
     assert dt < 5.0, dt
 
 
-@pytest.mark.parametrize("mode,wg", [("batched", 64), ("batched16", 64), ("batched", 128),
-                                     ("batched", 256)])
-def test_c3_4096_batched_exact_where_stored_and_valid_everywhere(opts, mode, wg):
+@pytest.mark.parametrize("mode,wg,cap", [("batched", 64, -1), ("batched16", 64, -1), ("batched", 128, -1),
+                                         ("batched", 256, -1), ("batched", 64, 640), ("batched", 64, 768)])
+def test_c3_4096_batched_exact_where_stored_and_valid_everywhere(opts, mode, wg, cap):
     """The 4096-state uneven workload in one persistent launch (the grid is
     smaller than the batch): exact against the stored oracle results, and
     every instance consistent with its walk and its heuristic, for every
-    workgroup size.  With 16-node rounds every pruned child's f is tracked
-    and each limit advance checks f_next = L + 2 on the device."""
+    workgroup size and for the small stacks (more waves, more spills).  With
+    16-node rounds every pruned child's f is tracked and each limit advance
+    checks f_next = L + 2 on the device."""
     B = opts
     from paper_1705_02843_amd import instances as I
-    _say("case: c3_uneven, 4096 states, %s, wg_size %d" % (mode, wg))
+    _say("case: c3_uneven, 4096 states, %s, wg_size %d, stack %d" % (mode, wg, cap))
     states, walk = I.c3_uneven()
     set_mode(B, mode)
     B.set_option("wg_size", wg)
+    B.set_option("lds_stack_capacity", cap)
     rc, ln, nodes = B.solve_raw(states)
     assert rc == B.OK, B.strerror(rc)
     name = "c3_uneven" if os.path.exists(os.path.join(GOLDEN, "c3_uneven.json")) else \
