@@ -595,6 +595,9 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   // 64-node rounds on 3x3 and 4x4 stacks store without branches (under the
   // keep mask)
   constexpr bool kMasked = NPL == 64 && sizeof(S) == 8;
+  // the width-4 64-node round keeps its stack meta in its own layout; chunks
+  // carry the common one
+  constexpr bool kMeta4 = NPL == 64 && W == 4;
   constexpr int kCap = CAP;
   const LaneMap M = make_lane_map(lane);
   const RoundConsts4 rk = make_round_consts4();
@@ -642,8 +645,8 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
           const uint16_t mg = sm[2 * lane], mk = sm[2 * lane + 1];
           WAVE_SYNC();
           if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
-          if (q_push(A, (uint64_t)tg, wide ? (uint64_t)((unsigned __int128)tg >> 64) : 0ull, mg, h,
-                     inst, wide)) {
+          if (q_push(A, (uint64_t)tg, wide ? (uint64_t)((unsigned __int128)tg >> 64) : 0ull,
+                     kMeta4 ? (uint16_t)meta4_out(mg) : mg, h, inst, wide)) {
             wc.pushes += 1;
             wc.voluntary += 1;
             // the kept half becomes the bottom, the entries above the window
@@ -669,8 +672,8 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
         const uint16_t m = sm[lane];
         WAVE_SYNC();
         if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
-        if (q_push(A, (uint64_t)t, wide ? (uint64_t)((unsigned __int128)t >> 64) : 0ull, m, 64,
-                   inst, wide)) {
+        if (q_push(A, (uint64_t)t, wide ? (uint64_t)((unsigned __int128)t >> 64) : 0ull,
+                   kMeta4 ? (uint16_t)meta4_out(m) : m, 64, inst, wide)) {
           wc.pushes += 1;
         } else if (lane == 0) {
           __hip_atomic_fetch_add(&A.is[inst].outstanding, -1, __ATOMIC_RELAXED, AGENT);
@@ -847,7 +850,8 @@ __global__ __launch_bounds__(64 * WPG, (batch_waves_per_simd<CAP, NPL>())) void 
     if (width == 4) {
       if (lane < cnt) {
         st[lane] = t;
-        sm[lane] = m;
+        // the 64-node round's stack has its own meta layout
+        sm[lane] = NPL == 64 ? (uint16_t)meta4_in(m) : m;
       }
       WAVE_SYNC();
       ok = A.first_solution

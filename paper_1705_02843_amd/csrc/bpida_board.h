@@ -207,60 +207,232 @@ __device__ __forceinline__ uint64_t opaque64(uint64_t v) {
   return v;
 }
 
-// Constants of the width-4 round, held in vector registers for a whole unit:
-// the four moves' up tables (bit "index" is Board<4>::up for that index),
-// the goal and the legal-move table.  Set once before the rounds instead of
-// once per round.
-struct RoundConsts4 {
-  uint32_t up[4];
-  uint64_t goal;
-  uint64_t legal;
-};
-
-// Move A's up table as Board<4>::up reads it: the table shifted by the
-// neighbour's offset, transposed for columns.
-template <int A>
-constexpr uint32_t up_table4() {
-  using B = Board<4>;
-  constexpr bool vert = A == 0 || A == 3;
-  constexpr int step = (A == 0 || A == 1) ? -1 : 1;
-  constexpr uint32_t tab = vert ? B::table(A) : B::transposed(B::table(A));
-  constexpr uint32_t sh = vert ? 1u : 4u;
-  return step < 0 ? (tab << sh) : (tab >> sh);
+// Hides a wave-uniform 32-bit constant from the optimiser and keeps it in a
+// scalar register (the operand of a class test below would otherwise be
+// folded into a mask-and-compare pair).
+__device__ __forceinline__ uint32_t opaque_s(uint32_t v) {
+  asm("" : "+s"(v));
+  return v;
 }
 
-// Compile-time proof: the round's lookup in these tables gives Board<4>::up
-// for every blank cell, move and tile.
-template <int A>
-constexpr bool check_up_table4() {
-  using B = Board<4>;
-  constexpr bool vert = A == 0 || A == 3;
+// ---------------------------------------------------------------------------
+// The width-4 64-node round.
+//
+// Its stack meta word is laid out for the round: slack / 2 in bits 0..5,
+// bits 6..7 zero, the blank cell in bits 8..11 and the forbidden move (4:
+// none) in bits 12..14.  m >> 6 then holds 4 x blank in its low six bits
+// (all that a 64-bit shift reads), and a child's slack / 2 is its parent's
+// minus a borrow.  Slack / 2 fits six bits: f never falls below h0 along a
+// path (Manhattan distance is consistent) and a limit is at most h0 + 126
+// (64 limits).  Queue chunks and split-tree roots carry the common layout
+// (blank | forbidden << 5 | slack << 8); meta4_in and meta4_out convert at
+// the stack's edges.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr uint32_t meta4_in(uint32_t m) {
+  return ((m >> 9) & 63u) | ((m & 15u) << 8) | (((m >> 5) & 7u) << 12);
+}
+__host__ __device__ constexpr uint32_t meta4_out(uint32_t m) {
+  return ((m >> 8) & 15u) | (((m >> 12) & 7u) << 5) | ((m & 63u) << 9);
+}
+constexpr bool check_meta4() {
   for (uint32_t b = 0; b < 16; ++b)
-    for (uint32_t t = 0; t < 16; ++t) {
-      const uint32_t rp = B::row_part(b), cp = B::col_part(b);
-      const uint32_t idx = vert ? ((t & 12u) | rp) : ((t & 3u) | cp);
-      if (((up_table4<A>() >> idx) & 1u) != B::template up<A>(t, rp, cp)) return false;
-    }
+    for (uint32_t f = 0; f <= 4; ++f)
+      for (uint32_t s = 0; s <= 126; s += 2) {
+        const uint32_t m = b | (f << 5) | (s << 8);
+        const uint32_t k = meta4_in(m);
+        if (meta4_out(k) != m || (k & 63u) != s / 2 || ((k >> 6) & 63u) != 4 * b ||
+            ((k >> 12) & 7u) != f || k > 0xFFFFu)
+          return false;
+      }
   return true;
 }
-static_assert(check_up_table4<0>() && check_up_table4<1>() && check_up_table4<2>() &&
-                  check_up_table4<3>(),
-              "width-4 up tables disagree with Board::up");
+static_assert(check_meta4(), "width-4 stack meta does not round-trip");
+
+// Move A of the width-4 round takes tile t away from its goal cell (tile t's
+// goal cell is t): the coordinate that changes is the row for U and D, the
+// column for L and R, and the tile moves away when its goal coordinate lies
+// behind the neighbour's, seen from the blank.  With the blank's row part
+// b & 12, b | 3 and its column b & 3 these are single compares:
+//   U: t >> 2 < row(b)      <=> t < (b & 12)
+//   D: t >> 2 > row(b)      <=> t > (b | 3)
+//   L: t & 3  < col(b),   R: t & 3 > col(b).
+template <int A>
+__host__ __device__ constexpr bool up4(uint32_t t, uint32_t b) {
+  return A == 0 ? t < (b & 12u) : A == 1 ? (t & 3u) < (b & 3u) : A == 2 ? (t & 3u) > (b & 3u) : t > (b | 3u);
+}
+template <int A>
+constexpr bool check_up4() {
+  using B = Board<4>;
+  for (uint32_t b = 0; b < 16; ++b) {
+    if (((legal_table<4>() >> (4 * b + A)) & 1u) == 0) continue;  // (any value serves)
+    for (uint32_t t = 1; t < 16; ++t)
+      if (up4<A>(t, b) != (B::template up<A>(t, B::row_part(b), B::col_part(b)) != 0)) return false;
+  }
+  return true;
+}
+static_assert(check_up4<0>() && check_up4<1>() && check_up4<2>() && check_up4<3>(),
+              "width-4 compares disagree with Board::up");
+
+// Constants of the width-4 round, set once per unit: the goal and the
+// legal-move table in vector registers (as operands of a 64-bit compare or
+// shift they would be reloaded into scalar registers every round), and one
+// float per move whose IEEE class is bit A of a class test's mask (signaling
+// NaN, quiet NaN, -infinity, -normal), so that a class test against a node's
+// 4-bit move mask says whether move A is in it.
+struct RoundConsts4 {
+  uint64_t goal;
+  uint64_t legal;
+  uint32_t cls[4];
+};
 
 __device__ __forceinline__ RoundConsts4 make_round_consts4() {
   RoundConsts4 k;
-  k.up[0] = opaque(up_table4<0>());
-  k.up[1] = opaque(up_table4<1>());
-  k.up[2] = opaque(up_table4<2>());
-  k.up[3] = opaque(up_table4<3>());
   k.goal = opaque64(Board<4>::goal());
   k.legal = opaque64(legal_table<4>());
+  k.cls[0] = opaque_s(0x7F800001u);  // signaling NaN: class bit 0
+  k.cls[1] = opaque_s(0x7FC00000u);  // quiet NaN: class bit 1
+  k.cls[2] = opaque_s(0xFF800000u);  // -infinity: class bit 2
+  k.cls[3] = opaque_s(0xBF800000u);  // -1.0, a negative normal: class bit 3
   return k;
 }
 
 // Byte address of an LDS object (its offset in the workgroup's LDS).
 __device__ __forceinline__ uint32_t lds_addr(const void* p) {
   return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// Lanes whose mask lm holds the IEEE class of the float with bits c (one
+// compare into a scalar register pair; written out because the compiler
+// turns the ballot of a class test into a select and a second compare).
+__device__ __forceinline__ uint64_t class_lanes(uint32_t c, uint32_t lm) {
+  uint64_t r;
+  asm("v_cmp_class_f32_e64 %0, %1, %2" : "=s"(r) : "s"(c), "v"(lm));
+  return r;
+}
+
+// a minus the lane's bit of the wave mask u (a subtract with borrow-in).
+__device__ __forceinline__ uint32_t sub_lane_bit(uint32_t a, uint64_t u) {
+  uint32_t r;
+  uint64_t borrow_out;
+  asm("v_subb_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(r), "=s"(borrow_out) : "v"(a), "s"(u));
+  return r;
+}
+
+// Per-node values of the width-4 round shared by its four moves.
+struct Node4 {
+  uint32_t shb;    // 4 x blank in the low six bits (higher bits are ignored)
+  uint32_t sr_lo;  // low word of s >> 4b: the cells after the blank
+  uint32_t su_hi;  // high word of s << (63 - 4b): the cells before it
+  uint32_t lm;     // bit A: move A is legal and does not undo the parent's
+  uint32_t b12;    // blank & 12, blank | 3, blank & 3: the up compares' bounds
+  uint32_t b3;
+  uint32_t bc;
+  uint32_t mbase;  // the meta word without its forbidden move
+  uint64_t roomy;  // lanes with slack >= 2 (a child may move a tile away)
+};
+
+// One move of the width-4 round for every lane (see bp_round64_4).
+template <int CAP, int A>
+__device__ __forceinline__ void bp_move4(uint64_t* st, uint32_t& out, const uint64_t s, const Node4& c,
+                                         const RoundConsts4& rk) {
+  constexpr int delta = A == 0 ? -4 : A == 1 ? -1 : A == 2 ? 1 : 4;
+  constexpr uint32_t K = (A == 0 || A == 3) ? 0xFFFFu : 15u;
+  // cell b + d sits at bits 4d of s >> 4b (d > 0), and at bits 63 + 4d - 32
+  // of the high word of s << (63 - 4b) (d < 0): one extract gives the tile
+  uint32_t x;
+  if constexpr (A == 0) x = (c.su_hi >> 15) & 15u;
+  else if constexpr (A == 1) x = (c.su_hi >> 27) & 15u;
+  else if constexpr (A == 2) x = (c.sr_lo >> 4) & 15u;
+  else x = (c.sr_lo >> 16) & 15u;
+  const uint32_t t = opaque(x);
+  bool up;  // the move takes t away from its goal cell (up4)
+  if constexpr (A == 0) up = t < c.b12;
+  else if constexpr (A == 1) up = (t & 3u) < c.bc;
+  else if constexpr (A == 2) up = (t & 3u) > c.bc;
+  else up = t > c.b3;
+  const uint64_t um = __builtin_amdgcn_ballot_w64(up);
+  // legal and not undoing: one class test of move A's constant against lm
+  const uint64_t lg = class_lanes(rk.cls[A], c.lm);
+  // kept: legal, and approaching its goal or with slack to spare (an away
+  // move costs 2 of slack; slack is even, so 0 prunes it)
+  const uint64_t km = lg & ~(um & ~c.roomy);
+  // successor: t moves from n = b + delta to b, i.e. the packed word changes
+  // by +/- (K * t) << (4 * min(b, n))
+  uint64_t cs;
+  if constexpr (A >= 2) {
+    // the subtraction as the addition of -K t sign-extended to 64 bits
+    const uint32_t nkt = mul_i24(-(int)K, t);
+    cs = s + (((0xFFFFFFFFull << 32) | nkt) << (c.shb & 63u));
+  } else {
+    const uint32_t kt = mul_u24(K, t);
+    cs = s + ((uint64_t)kt << ((c.shb + (uint32_t)(4 * delta)) & 63u));
+  }
+  // child meta: slack / 2 minus up (a borrow), blank n, forbidden 3 - A
+  const uint32_t cm = sub_lane_bit(c.mbase + (uint32_t)(delta * 256 + (3 - A) * 4096), um);
+  const uint32_t r =
+      __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+  // byte offsets into the stack: entry out + r (below CAP: the caller leaves
+  // room for the largest round).  The two stores run under the keep mask
+  // with no branch around them (the meta array follows the CAP tiles); the
+  // compiler would put a skip jump around stores in a divergent branch, so
+  // this asm sets EXEC to the mask, stores and restores EXEC itself.
+  const uint32_t pst = (r + out) << 3;
+  const uint32_t as = lds_addr(st) + pst;
+  const uint32_t am = lds_addr(st) + (pst >> 2);
+  uint64_t saved;
+  asm volatile(
+      "s_and_saveexec_b64 %0, %1\n\t"
+      "ds_write_b64 %2, %3\n\t"
+      "ds_write_b16 %4, %5 offset:%6\n\t"
+      "s_mov_b64 exec, %0"
+      : "=&s"(saved)
+      : "s"(km), "v"(as), "v"(cs), "v"(am), "v"(cm), "i"(CAP * 8)
+      : "memory", "scc");
+  out += (uint32_t)__popcll(km);
+}
+
+// One BPDFS round of the width-4 board with one popped node per lane: pops
+// kp = min(64, top) nodes from a stack of entries [0, top) (CAP tiles, then
+// CAP meta words in the width-4 layout), tests them for the goal and pushes
+// every legal, non-undoing child with f <= limit.  The caller guarantees
+// that the children fit, top + 2*kp <= CAP; FULL: kp = 64 and `goals` is a
+// 64-bit mask that collects the lanes that expanded a goal, else a count.
+// Pruned children are not tracked: every slack on the stack is even (f
+// keeps the parity of h0, and so does the limit), so a child is pruned only
+// from slack 0, moving a tile away from its goal, and its f is the limit + 2.
+template <int CAP, bool FULL, typename G>
+__device__ __forceinline__ uint32_t bp_round64_4(uint64_t* st, uint32_t top, int kp, G& goals,
+                                                 const RoundConsts4& rk) {
+  const int lane = lane_id();
+  const uint32_t base = top - (uint32_t)kp;
+  const uint32_t pst = opaque((base + (uint32_t)lane) << 3);
+  const uint64_t s = *(const uint64_t*)((const char*)st + pst);
+  const uint32_t m = *(const uint16_t*)((const char*)(st + CAP) + (pst >> 2));
+  const uint64_t actm = FULL || kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
+  const uint64_t gm = __builtin_amdgcn_uicmpl(s, rk.goal, 32);
+  if constexpr (FULL) goals |= gm;
+  else goals += __popcll(gm & actm);
+  Node4 c;
+  c.shb = opaque(m >> 6);
+  c.sr_lo = (uint32_t)(s >> (c.shb & 63u));
+  c.su_hi = (uint32_t)((s << (~c.shb & 63u)) >> 32);
+  const uint32_t fb = (m >> 12) & 7u;
+  const uint32_t lm = (uint32_t)(rk.legal >> (c.shb & 63u)) & ~(1u << fb) & 15u;
+  // lanes past kp keep nothing
+  c.lm = FULL ? lm : sel_lanes(actm, lm);
+  c.roomy = __builtin_amdgcn_ballot_w64((m & 63u) != 0u);
+  const uint32_t b = (m >> 8) & 15u;
+  c.b12 = b & 12u;
+  c.b3 = b | 3u;
+  c.bc = b & 3u;
+  c.mbase = m & 0x0FFFu;
+  uint32_t out = base;
+  bp_move4<CAP, 0>(st, out, s, c, rk);
+  bp_move4<CAP, 1>(st, out, s, c, rk);
+  bp_move4<CAP, 2>(st, out, s, c, rk);
+  bp_move4<CAP, 3>(st, out, s, c, rk);
+  WAVE_SYNC();
+  return out;
 }
 
 // Per-node values shared by the four moves of a 64-node round.
@@ -271,15 +443,12 @@ struct NodeCtx {
   uint32_t coli;   // horizontal moves: the blank's column (x W for width 4)
   uint32_t lmx;    // bit (A + 4 up): move A survives the f test
   uint32_t mbase;  // slack << 8 | blank
-  uint32_t sr_lo;  // width 4: low word of s >> 4b (the cells after the blank)
-  uint32_t su_hi;  // width 4: high word of s << (63 - 4b) (the cells before it)
 };
 
 // One move for every lane of a 64-node round (see bp_round64w).
 template <int W, int CAP, int A, bool MASKED>
 __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm, uint32_t& out,
-                                          const typename Board<W>::S s, const NodeCtx& c,
-                                          const RoundConsts4& rk) {
+                                          const typename Board<W>::S s, const NodeCtx& c) {
   using B = Board<W>;
   using S = typename B::S;
   constexpr int delta = A == 0 ? -W : A == 1 ? -1 : A == 2 ? 1 : W;
@@ -288,24 +457,9 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
   // shift to the neighbour's cell; it wraps (and the tile is unused) when
   // the move is illegal, and needs no mask on a legal one
   const uint32_t shu = c.shb + (uint32_t)(B::BITS * delta);
-  uint32_t tile;  // the neighbour's tile t
-  uint32_t up;    // 1 iff the move takes t away from its goal cell
-  if constexpr (W == 4) {
-    // cell b + d sits at bits 4d of s >> 4b (d > 0), and at bits 63 + 4d - 32
-    // of the high word of s << (63 - 4b) (d < 0): one extract gives the tile
-    // alone, for the table index and for the successor
-    uint32_t x;
-    if constexpr (A == 0) x = (c.su_hi >> 15) & 15u;
-    else if constexpr (A == 1) x = (c.su_hi >> 27) & 15u;
-    else if constexpr (A == 2) x = (c.sr_lo >> 4) & 15u;
-    else x = (c.sr_lo >> 16) & 15u;
-    tile = opaque(x);
-    up = (rk.up[A] >> (vert ? (tile & 12u) | c.rowi : (tile & 3u) | c.coli)) & 1u;
-  } else {
-    const uint32_t x = (uint32_t)(s >> (shu & (8u * sizeof(S) - 1u)));
-    tile = x & B::MASK;
-    up = B::template up<A>(x, c.rowi, c.coli);
-  }
+  const uint32_t x = (uint32_t)(s >> (shu & (8u * sizeof(S) - 1u)));
+  const uint32_t tile = x & B::MASK;  // the neighbour's tile t
+  const uint32_t up = B::template up<A>(x, c.rowi, c.coli);  // 1: t moves away from its goal cell
   const uint32_t kb = opaque((c.lmx >> (A + 4 * up)) & 1u);
   const uint64_t km = __builtin_amdgcn_uicmp(kb, 0u, 33);  // lanes with kb != 0
   // MASKED (64-bit states): every lane builds its child (a vector
@@ -361,7 +515,8 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
   out += (uint32_t)__popcll(km);
 }
 
-// One BPDFS round with one popped node per lane, for any board width: pops
+// One BPDFS round with one popped node per lane, for boards of width 3 and
+// 5 (width 4 has its own round above, with its own stack meta layout): pops
 // kp = min(64, top) nodes from a stack of entries [0, top), tests them for
 // the goal and pushes every legal, non-undoing child with f <= limit.  The
 // caller guarantees that the children fit, top + 2*kp <= CAP (three
@@ -375,54 +530,48 @@ __device__ __forceinline__ void bp_move_w(typename Board<W>::S* st, uint16_t* sm
 template <int W, int CAP, bool MASKED, bool FULL, typename G>
 __device__ __forceinline__ uint32_t bp_round64w(typename Board<W>::S* st, uint16_t* sm, uint32_t top, int kp,
                                            G& goals, const RoundConsts4& rk) {
-  using B = Board<W>;
-  using S = typename B::S;
-  const int lane = lane_id();
-  const uint32_t base = top - (uint32_t)kp;
-  constexpr uint32_t LS = sizeof(S) == 8 ? 3 : 4;
-  const uint32_t pst = opaque((base + (uint32_t)lane) << LS);
-  const S s = *(const S*)((const char*)st + pst);
-  const uint32_t m = *(const uint16_t*)((const char*)sm + (pst >> (LS - 1)));
-  const uint64_t actm = FULL || kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
-  uint64_t gm;
-  if constexpr (W == 4) gm = __builtin_amdgcn_uicmpl((uint64_t)s, rk.goal, 32);
-  else if constexpr (sizeof(S) == 8) gm = __builtin_amdgcn_uicmpl((uint64_t)s, (uint64_t)B::goal(), 32);
-  else gm = __builtin_amdgcn_ballot_w64(s == B::goal());
-  // goals: a count (int), or (FULL) the union of the rounds' goal masks
-  if constexpr (FULL) goals |= gm;
-  else goals += __popcll(gm & actm);
-  NodeCtx c;
-  c.b = m & 31u;
-  const uint32_t fb = (m >> 5) & 7u;
-  uint32_t lm;
   if constexpr (W == 4) {
-    // m << 2 has 4b in its low six bits, all that a 64-bit shift reads
-    c.shb = opaque(m << 2);
-    c.sr_lo = (uint32_t)(s >> (c.shb & 63u));
-    c.su_hi = (uint32_t)((s << (~c.shb & 63u)) >> 32);
-    lm = (uint32_t)(rk.legal >> (c.shb & 63u)) & ~(1u << fb) & 15u;
-    c.coli = c.shb & 12u;
+    return bp_round64_4<CAP, FULL>(st, top, kp, goals, rk);
   } else {
+    using B = Board<W>;
+    using S = typename B::S;
+    const int lane = lane_id();
+    const uint32_t base = top - (uint32_t)kp;
+    constexpr uint32_t LS = sizeof(S) == 8 ? 3 : 4;
+    const uint32_t pst = opaque((base + (uint32_t)lane) << LS);
+    const S s = *(const S*)((const char*)st + pst);
+    const uint32_t m = *(const uint16_t*)((const char*)sm + (pst >> (LS - 1)));
+    const uint64_t actm = FULL || kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
+    uint64_t gm;
+    if constexpr (sizeof(S) == 8) gm = __builtin_amdgcn_uicmpl((uint64_t)s, (uint64_t)B::goal(), 32);
+    else gm = __builtin_amdgcn_ballot_w64(s == B::goal());
+    // goals: a count (int), or (FULL) the union of the rounds' goal masks
+    if constexpr (FULL) goals |= gm;
+    else goals += __popcll(gm & actm);
+    NodeCtx c;
+    c.b = m & 31u;
+    const uint32_t fb = (m >> 5) & 7u;
     c.shb = opaque(B::BITS * c.b);
+    uint32_t lm;
     if constexpr (W * W <= 16) lm = (uint32_t)(legal_table<W>() >> (4u * c.b)) & ~(1u << fb) & 15u;
     else lm = B::legal(c.b) & ~(1u << fb);
     c.coli = B::col_part(c.b);
+    c.rowi = B::row_part(c.b);
+    // moves that survive: any legal one if its tile approaches its goal, and
+    // only with slack >= 2 if it moves away (bits 0..3 and 4..7 of lm * 17);
+    // lanes past kp keep nothing
+    const bool roomy = m >= (2u << 8);
+    if constexpr (FULL) c.lmx = mul_u24(lm, roomy ? 17u : 1u);
+    else c.lmx = mul_u24(lm, sel_lanes(actm, roomy ? 17u : 1u));
+    c.mbase = (m & 0xFF00u) | c.b;
+    uint32_t out = base;
+    bp_move_w<W, CAP, 0, MASKED>(st, sm, out, s, c);
+    bp_move_w<W, CAP, 1, MASKED>(st, sm, out, s, c);
+    bp_move_w<W, CAP, 2, MASKED>(st, sm, out, s, c);
+    bp_move_w<W, CAP, 3, MASKED>(st, sm, out, s, c);
+    WAVE_SYNC();
+    return out;
   }
-  c.rowi = B::row_part(c.b);
-  // moves that survive: any legal one if its tile approaches its goal, and
-  // only with slack >= 2 if it moves away (bits 0..3 and 4..7 of lm * 17);
-  // lanes past kp keep nothing
-  const bool roomy = m >= (2u << 8);
-  if constexpr (FULL) c.lmx = mul_u24(lm, roomy ? 17u : 1u);
-  else c.lmx = mul_u24(lm, sel_lanes(actm, roomy ? 17u : 1u));
-  c.mbase = (m & 0xFF00u) | c.b;
-  uint32_t out = base;
-  bp_move_w<W, CAP, 0, MASKED>(st, sm, out, s, c, rk);
-  bp_move_w<W, CAP, 1, MASKED>(st, sm, out, s, c, rk);
-  bp_move_w<W, CAP, 2, MASKED>(st, sm, out, s, c, rk);
-  bp_move_w<W, CAP, 3, MASKED>(st, sm, out, s, c, rk);
-  WAVE_SYNC();
-  return out;
 }
 
 }  // namespace bpida

@@ -360,7 +360,8 @@ __global__ __launch_bounds__(64) void search64_kernel(const Node* __restrict__ r
     }
     if (lane == 0) {
       st[0] = R.tiles;
-      sm[0] = (uint16_t)((R.meta & 0xFFu) | ((uint32_t)(limit - (int)R.f) << 8));
+      // (the width-4 round's stack meta layout)
+      sm[0] = (uint16_t)meta4_in((R.meta & 0xFFu) | ((uint32_t)(limit - (int)R.f) << 8));
     }
     WAVE_SYNC();
     const uint64_t rounds0 = rounds;
