@@ -219,20 +219,24 @@ __device__ __forceinline__ uint32_t opaque_s(uint32_t v) {
 // The width-4 64-node round.
 //
 // Its stack meta word is laid out for the round: slack / 2 in bits 0..5,
-// bits 6..7 zero, the blank cell in bits 8..11 and the forbidden move (4:
-// none) in bits 12..14.  m >> 6 then holds 4 x blank in its low six bits
-// (all that a 64-bit shift reads), and a child's slack / 2 is its parent's
-// minus a borrow.  Slack / 2 fits six bits: f never falls below h0 along a
+// bits 6..7 zero, the blank cell in bits 8..11 and the forbidden move as a
+// one-hot mask in bits 12..15 (0: none).  m >> 6 then holds 4 x blank in
+// its low six bits (all that a 64-bit shift reads), byte 0 is slack / 2
+// and byte 1 the blank plus the mask, and a child's slack / 2 is its
+// parent's minus a borrow.  Slack / 2 fits six bits: f never falls below h0 along a
 // path (Manhattan distance is consistent) and a limit is at most h0 + 126
 // (64 limits).  Queue chunks and split-tree roots carry the common layout
 // (blank | forbidden << 5 | slack << 8); meta4_in and meta4_out convert at
 // the stack's edges.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr uint32_t meta4_in(uint32_t m) {
-  return ((m >> 9) & 63u) | ((m & 15u) << 8) | (((m >> 5) & 7u) << 12);
+  const uint32_t fb = (m >> 5) & 7u;
+  return ((m >> 9) & 63u) | ((m & 15u) << 8) | ((fb < 4u ? 1u << fb : 0u) << 12);
 }
 __host__ __device__ constexpr uint32_t meta4_out(uint32_t m) {
-  return ((m >> 8) & 15u) | (((m >> 12) & 7u) << 5) | ((m & 63u) << 9);
+  const uint32_t f = (m >> 12) & 15u;
+  const uint32_t fb = f == 0u ? 4u : f == 1u ? 0u : f == 2u ? 1u : f == 4u ? 2u : 3u;
+  return ((m >> 8) & 15u) | (fb << 5) | ((m & 63u) << 9);
 }
 constexpr bool check_meta4() {
   for (uint32_t b = 0; b < 16; ++b)
@@ -241,7 +245,7 @@ constexpr bool check_meta4() {
         const uint32_t m = b | (f << 5) | (s << 8);
         const uint32_t k = meta4_in(m);
         if (meta4_out(k) != m || (k & 63u) != s / 2 || ((k >> 6) & 63u) != 4 * b ||
-            ((k >> 12) & 7u) != f || k > 0xFFFFu)
+            ((k >> 12) & 15u) != (f < 4u ? 1u << f : 0u) || k > 0xFFFFu)
           return false;
       }
   return true;
@@ -318,16 +322,33 @@ __device__ __forceinline__ uint32_t sub_lane_bit(uint32_t a, uint64_t u) {
   return r;
 }
 
+// Lanes whose byte 0 of v is nonzero (one compare with a byte select).
+__device__ __forceinline__ uint64_t byte0_lanes(uint32_t v) {
+  uint64_t r;
+  asm("v_cmp_ne_u32_sdwa %0, %1, 0 src0_sel:BYTE_0 src1_sel:DWORD" : "=s"(r) : "v"(v));
+  return r;
+}
+
+// K AND byte 1 of v (one instruction with a byte select).
+template <int K>
+__device__ __forceinline__ uint32_t and_byte1(uint32_t v) {
+  uint32_t r;
+  asm("v_and_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+      : "=v"(r)
+      : "i"(K), "v"(v));
+  return r;
+}
+
 // Per-node values of the width-4 round shared by its four moves.
 struct Node4 {
   uint32_t shb;    // 4 x blank in the low six bits (higher bits are ignored)
   uint32_t sr_lo;  // low word of s >> 4b: the cells after the blank
   uint32_t su_hi;  // high word of s << (63 - 4b): the cells before it
-  uint32_t lm;     // bit A: move A is legal and does not undo the parent's
+  uint32_t lm;     // bit A (A < 4): move A is legal and does not undo the parent's
   uint32_t b12;    // blank & 12, blank | 3, blank & 3: the up compares' bounds
   uint32_t b3;
   uint32_t bc;
-  uint32_t mbase;  // the meta word without its forbidden move
+  uint32_t mbase;  // the meta word without its forbidden-move mask
   uint64_t roomy;  // lanes with slack >= 2 (a child may move a tile away)
 };
 
@@ -368,7 +389,7 @@ __device__ __forceinline__ void bp_move4(uint64_t* st, uint32_t& out, const uint
     cs = s + ((uint64_t)kt << ((c.shb + (uint32_t)(4 * delta)) & 63u));
   }
   // child meta: slack / 2 minus up (a borrow), blank n, forbidden 3 - A
-  const uint32_t cm = sub_lane_bit(c.mbase + (uint32_t)(delta * 256 + (3 - A) * 4096), um);
+  const uint32_t cm = sub_lane_bit(c.mbase + (uint32_t)(delta * 256 + (4096 << (3 - A))), um);
   const uint32_t r =
       __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
   // byte offsets into the stack: entry out + r (below CAP: the caller leaves
@@ -416,15 +437,15 @@ __device__ __forceinline__ uint32_t bp_round64_4(uint64_t* st, uint32_t top, int
   c.shb = opaque(m >> 6);
   c.sr_lo = (uint32_t)(s >> (c.shb & 63u));
   c.su_hi = (uint32_t)((s << (~c.shb & 63u)) >> 32);
-  const uint32_t fb = (m >> 12) & 7u;
-  const uint32_t lm = (uint32_t)(rk.legal >> (c.shb & 63u)) & ~(1u << fb) & 15u;
+  // legal moves minus the forbidden one; bits above 3 (the next cells'
+  // legal moves) are left in: the class tests read only bits 0..3
+  const uint32_t lm = (uint32_t)(rk.legal >> (c.shb & 63u)) & ~(m >> 12);
   // lanes past kp keep nothing
   c.lm = FULL ? lm : sel_lanes(actm, lm);
-  c.roomy = __builtin_amdgcn_ballot_w64((m & 63u) != 0u);
-  const uint32_t b = (m >> 8) & 15u;
-  c.b12 = b & 12u;
-  c.b3 = b | 3u;
-  c.bc = b & 3u;
+  c.roomy = byte0_lanes(m);  // slack / 2 != 0
+  c.b12 = and_byte1<12>(m);  // byte 1 = blank | mask << 4
+  c.b3 = c.b12 | 3u;
+  c.bc = and_byte1<3>(m);
   c.mbase = m & 0x0FFFu;
   uint32_t out = base;
   bp_move4<CAP, 0>(st, out, s, c, rk);
