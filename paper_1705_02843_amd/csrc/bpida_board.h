@@ -287,7 +287,14 @@ struct RoundConsts4 {
   uint64_t goal;
   uint64_t legal;
   uint32_t cls[4];
+  uint32_t nk[4];  // per move, minus its child's meta increment (vector registers)
 };
+
+// Move A's child meta increment: blank + delta, forbidden move 3 - A.
+template <int A>
+constexpr int meta4_step() {
+  return (A == 0 ? -4 : A == 1 ? -1 : A == 2 ? 1 : 4) * 256 + (4096 << (3 - A));
+}
 
 __device__ __forceinline__ RoundConsts4 make_round_consts4() {
   RoundConsts4 k;
@@ -297,6 +304,10 @@ __device__ __forceinline__ RoundConsts4 make_round_consts4() {
   k.cls[1] = opaque_s(0x7FC00000u);  // quiet NaN: class bit 1
   k.cls[2] = opaque_s(0xFF800000u);  // -infinity: class bit 2
   k.cls[3] = opaque_s(0xBF800000u);  // -1.0, a negative normal: class bit 3
+  k.nk[0] = opaque((uint32_t)-meta4_step<0>());
+  k.nk[1] = opaque((uint32_t)-meta4_step<1>());
+  k.nk[2] = opaque((uint32_t)-meta4_step<2>());
+  k.nk[3] = opaque((uint32_t)-meta4_step<3>());
   return k;
 }
 
@@ -311,14 +322,6 @@ __device__ __forceinline__ uint32_t lds_addr(const void* p) {
 __device__ __forceinline__ uint64_t class_lanes(uint32_t c, uint32_t lm) {
   uint64_t r;
   asm("v_cmp_class_f32_e64 %0, %1, %2" : "=s"(r) : "s"(c), "v"(lm));
-  return r;
-}
-
-// a minus the lane's bit of the wave mask u (a subtract with borrow-in).
-__device__ __forceinline__ uint32_t sub_lane_bit(uint32_t a, uint64_t u) {
-  uint32_t r;
-  uint64_t borrow_out;
-  asm("v_subb_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(r), "=s"(borrow_out) : "v"(a), "s"(u));
   return r;
 }
 
@@ -337,6 +340,35 @@ __device__ __forceinline__ uint32_t and_byte1(uint32_t v) {
       : "=v"(r)
       : "i"(K), "v"(v));
   return r;
+}
+
+// The up compare, keep mask and child meta of one width-4 move, with the
+// compare's lane mask in VCC: up = x < y (LT) or x > y; keep = legal and
+// not (up and not roomy); meta = base - nk - up, one subtract with the
+// borrow taken from VCC (nk: the move's meta increment, negated, in a vector
+// register; the borrow-in already uses the one scalar operand the
+// instruction may read, so the constant cannot be a literal).
+template <bool LT>
+__device__ __forceinline__ void keep_meta(uint32_t x, uint32_t y, uint64_t legal, uint64_t roomy,
+                                          uint32_t base, uint32_t nk, uint64_t& keep, uint32_t& meta) {
+  uint64_t away_short;
+  if constexpr (LT) {
+    asm("v_cmp_lt_u32_e32 vcc, %[x], %[y]\n\t"
+        "s_andn2_b64 %[t], vcc, %[r]\n\t"
+        "s_andn2_b64 %[k], %[l], %[t]\n\t"
+        "v_subb_co_u32_e32 %[m], vcc, %[b], %[nk], vcc"
+        : [k] "=&s"(keep), [m] "=v"(meta), [t] "=&s"(away_short)
+        : [x] "v"(x), [y] "v"(y), [l] "s"(legal), [r] "s"(roomy), [b] "v"(base), [nk] "v"(nk)
+        : "vcc", "scc");
+  } else {
+    asm("v_cmp_gt_u32_e32 vcc, %[x], %[y]\n\t"
+        "s_andn2_b64 %[t], vcc, %[r]\n\t"
+        "s_andn2_b64 %[k], %[l], %[t]\n\t"
+        "v_subb_co_u32_e32 %[m], vcc, %[b], %[nk], vcc"
+        : [k] "=&s"(keep), [m] "=v"(meta), [t] "=&s"(away_short)
+        : [x] "v"(x), [y] "v"(y), [l] "s"(legal), [r] "s"(roomy), [b] "v"(base), [nk] "v"(nk)
+        : "vcc", "scc");
+  }
 }
 
 // Per-node values of the width-4 round shared by its four moves.
@@ -366,17 +398,18 @@ __device__ __forceinline__ void bp_move4(uint64_t* st, uint32_t& out, const uint
   else if constexpr (A == 2) x = (c.sr_lo >> 4) & 15u;
   else x = (c.sr_lo >> 16) & 15u;
   const uint32_t t = opaque(x);
-  bool up;  // the move takes t away from its goal cell (up4)
-  if constexpr (A == 0) up = t < c.b12;
-  else if constexpr (A == 1) up = (t & 3u) < c.bc;
-  else if constexpr (A == 2) up = (t & 3u) > c.bc;
-  else up = t > c.b3;
-  const uint64_t um = __builtin_amdgcn_ballot_w64(up);
+  // the move takes t away from its goal cell (up4): U t < b & 12, L
+  // (t & 3) < b & 3, R (t & 3) > b & 3, D t > b | 3
+  const uint32_t ux = (A == 1 || A == 2) ? (t & 3u) : t;
+  const uint32_t uy = A == 0 ? c.b12 : A == 3 ? c.b3 : c.bc;
   // legal and not undoing: one class test of move A's constant against lm
   const uint64_t lg = class_lanes(rk.cls[A], c.lm);
   // kept: legal, and approaching its goal or with slack to spare (an away
-  // move costs 2 of slack; slack is even, so 0 prunes it)
-  const uint64_t km = lg & ~(um & ~c.roomy);
+  // move costs 2 of slack; slack is even, so 0 prunes it); child meta:
+  // slack / 2 minus up (a borrow), blank n, forbidden 3 - A
+  uint64_t km;
+  uint32_t cm;
+  keep_meta<(A == 0 || A == 1)>(ux, uy, lg, c.roomy, c.mbase, rk.nk[A], km, cm);
   // successor: t moves from n = b + delta to b, i.e. the packed word changes
   // by +/- (K * t) << (4 * min(b, n))
   uint64_t cs;
@@ -388,8 +421,6 @@ __device__ __forceinline__ void bp_move4(uint64_t* st, uint32_t& out, const uint
     const uint32_t kt = mul_u24(K, t);
     cs = s + ((uint64_t)kt << ((c.shb + (uint32_t)(4 * delta)) & 63u));
   }
-  // child meta: slack / 2 minus up (a borrow), blank n, forbidden 3 - A
-  const uint32_t cm = sub_lane_bit(c.mbase + (uint32_t)(delta * 256 + (4096 << (3 - A))), um);
   const uint32_t r =
       __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
   // byte offsets into the stack: entry out + r (below CAP: the caller leaves
