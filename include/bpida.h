@@ -250,12 +250,14 @@ int bpida_server_stop(void);
  *   "frontier_depth"     depth D of the root split, 0..16, or -1 (default):
  *                        10 in plain mode, 6 in batched mode
  *   "lds_stack_capacity" DFS stack entries per workgroup in LDS: 128, 256,
- *                        512, 640, 768, 1024 or 2048, or -1 (default): 512 for
- *                        16-node rounds, 1024 for 64-node rounds (64-node
+ *                        512, 640, 672, 768, 1024 or 2048, or -1 (default): 512
+ *                        for 16-node rounds, 1024 for 64-node rounds (64-node
  *                        rounds need at least 512 on 4x4 and 1024 on 5x5, 256
- *                        on 3x3; 640 and 768 only for batched 64-node rounds
- *                        with one-wave workgroups, where they let 24 and 20
- *                        waves share a compute unit instead of 16; other
+ *                        on 3x3; 640, 672 and 768 only for batched 64-node
+ *                        rounds with one-wave workgroups, where they let 24,
+ *                        20 and 20 waves share a compute unit instead of 16;
+ *                        at 672 the 4x4 stack interleaves each entry's state
+ *                        and meta word, one instruction less per child; other
  *                        combinations are BPIDA_EINVAL at solve time); deeper
  *                        entries spill to HBM (plain) or to the work queue
  *                        (batched).  A smaller stack spills more: with 512

@@ -39,7 +39,7 @@ def axes(grid_full: int):
     """The values swept per axis; (nodes per round, stack capacity) move
     together."""
     return [
-        ("round", [(16, 512), (64, 512), (64, 640), (64, 768), (64, 1024), (64, 2048)]),
+        ("round", [(16, 512), (64, 512), (64, 640), (64, 672), (64, 768), (64, 1024), (64, 2048)]),
         ("wg_size", [64, 128, 256]),
         ("frontier_depth", [4, 5, 6, 7, 8, 9, 10]),
         ("max_workgroups", [0, grid_full // 2]),

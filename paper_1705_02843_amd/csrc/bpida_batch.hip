@@ -595,8 +595,8 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   // 64-node rounds on 3x3 and 4x4 stacks store without branches (under the
   // keep mask)
   constexpr bool kMasked = NPL == 64 && sizeof(S) == 8;
-  // the width-4 64-node round keeps its stack meta in its own layout; chunks
-  // carry the common one
+  // the width-4 64-node round keeps its stack in its own layout (12-byte
+  // entries, its own meta word); chunks carry the common meta word
   constexpr bool kMeta4 = NPL == 64 && W == 4;
   constexpr int kCap = CAP;
   const LaneMap M = make_lane_map(lane);
@@ -641,8 +641,19 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
           const int w = min(avail, A.donate_window) & ~1;
           const int h = w >> 1;
           // (positions up to 127: inside the stack's storage, read for every lane)
-          const S tg = st[2 * lane], tk = st[2 * lane + 1];
-          const uint16_t mg = sm[2 * lane], mk = sm[2 * lane + 1];
+          S tg, tk;
+          uint16_t mg, mk;
+          if constexpr (kMeta4) {
+            tg = (S)e4_tile<CAP>((uint64_t*)st, 2 * lane);
+            tk = (S)e4_tile<CAP>((uint64_t*)st, 2 * lane + 1);
+            mg = (uint16_t)e4_meta<CAP>((uint64_t*)st, 2 * lane);
+            mk = (uint16_t)e4_meta<CAP>((uint64_t*)st, 2 * lane + 1);
+          } else {
+            tg = st[2 * lane];
+            tk = st[2 * lane + 1];
+            mg = sm[2 * lane];
+            mk = sm[2 * lane + 1];
+          }
           WAVE_SYNC();
           if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
           if (q_push(A, (uint64_t)tg, wide ? (uint64_t)((unsigned __int128)tg >> 64) : 0ull,
@@ -651,11 +662,17 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
             wc.voluntary += 1;
             // the kept half becomes the bottom, the entries above the window
             // close up behind it
-            if (lane < h) {
-              st[lane] = tk;
-              sm[lane] = mk;
+            if constexpr (kMeta4) {
+              if (lane < h) e4_put<CAP>((uint64_t*)st, lane, (uint64_t)tk, mk);
+              WAVE_SYNC();
+              move_down4<CAP>((uint64_t*)st, (uint32_t)h, (uint32_t)w, top - (uint32_t)w);
+            } else {
+              if (lane < h) {
+                st[lane] = tk;
+                sm[lane] = mk;
+              }
+              move_down(st, sm, (uint32_t)h, (uint32_t)w, top - (uint32_t)w);
             }
-            move_down(st, sm, (uint32_t)h, (uint32_t)w, top - (uint32_t)w);
             top -= (uint32_t)h;
             avail -= h;
           } else if (lane == 0) {
@@ -668,8 +685,8 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
       // LDS could overflow: move the oldest entries to the queue, 64 at a
       // time, until the largest round fits.
       do {
-        const S t = st[lane];
-        const uint16_t m = sm[lane];
+        const S t = kMeta4 ? (S)e4_tile<CAP>((uint64_t*)st, lane) : st[lane];
+        const uint16_t m = kMeta4 ? (uint16_t)e4_meta<CAP>((uint64_t*)st, lane) : sm[lane];
         WAVE_SYNC();
         if (lane == 0) __hip_atomic_fetch_add(&A.is[inst].outstanding, 1, __ATOMIC_RELAXED, AGENT);
         if (q_push(A, (uint64_t)t, wide ? (uint64_t)((unsigned __int128)t >> 64) : 0ull,
@@ -680,7 +697,8 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
           __hip_atomic_store(&A.is[inst].lost, 1, __ATOMIC_RELAXED, AGENT);
           atomicOr(&q->err, 2);  // entries dropped: the call reports BPIDA_ENOMEM
         }
-        move_down(st, sm, 0u, 64u, top - 64u);
+        if constexpr (kMeta4) move_down4<CAP>((uint64_t*)st, 0u, 64u, top - 64u);
+        else move_down(st, sm, 0u, 64u, top - 64u);
         top -= 64u;
         avail -= 64;
       } while (avail + kGrow > kCap);
@@ -738,18 +756,21 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
 
 // The persistent kernel.  A workgroup holds WPG independent waves (Sec. 5's
 // block = one warp, WPG times over): each wave has its own stack and takes
-// its own work, and no wave ever waits for another.  LDS per wave: a
-// 10*CAP-byte stack, CAP entries of u64 tiles + u16 meta for widths 3 and 4,
-// CAP/2 entries of 128-bit tiles + u16 meta for width 5; the width is read
-// per chunk from the instance.
+// its own work, and no wave ever waits for another.  LDS per wave: CAP
+// entries of u64 tiles + u16 meta for widths 3 and 4 (10 bytes an entry;
+// 12 for width 4 in the interleaved layout, which then sizes the stack for
+// every width), CAP/2 entries of 128-bit tiles + u16 meta for width 5; the
+// width is read per chunk from the instance.
 //
-// Waves per SIMD a one-wave workgroup's stack allows (LDS: 160 KB per
-// compute unit, 10 bytes an entry): 16 at 1024 entries, 20 at 768, 24 at
-// 640.  The launch bound keeps the vector registers within that occupancy
-// (at most 96 and 80 per lane).
+// Waves per SIMD a one-wave workgroup's 64-node stack allows (LDS: 160 KB
+// per compute unit): 24 per compute unit at 640 entries, 20 at 672
+// (interleaved) and 768, 16 at 1024.  The launch bound keeps the vector
+// registers within that occupancy (at most 80 per lane at 6 waves per SIMD,
+// 96 at 5), capped at 6.
 template <int CAP, int NPL>
 constexpr int batch_waves_per_simd() {
-  return NPL != 64 ? 1 : CAP <= 640 ? 6 : CAP <= 768 ? 5 : 1;
+  constexpr int w = NPL != 64 ? 1 : (int)(163840u / stack4_bytes<CAP>()) / 4;
+  return w > 6 ? 6 : w < 1 ? 1 : w;
 }
 
 template <int CAP, int NPL, int WPG>
@@ -758,7 +779,9 @@ __global__ __launch_bounds__(64 * WPG, (batch_waves_per_simd<CAP, NPL>())) void 
   static_assert(NPL == 16 || NPL == 64, "nodes per round");
   static_assert(NPL == 16 || CAP >= 256, "stack too small for 64-node rounds");
   static_assert(WPG == 1 || WPG == 2 || WPG == 4, "waves per workgroup");
-  constexpr int kWords = (10 * CAP) / 8;  // u64 words of one wave's stack
+  // u64 words of one wave's stack: 10 bytes an entry, or 12 with the
+  // interleaved width-4 layout of 64-node rounds
+  constexpr int kWords = (int)((NPL == 64 ? stack4_bytes<CAP>() : 10u * CAP) / 8u);
   __shared__ __attribute__((aligned(16))) uint64_t lds[WPG * kWords];
   uint64_t* st = lds + (WPG == 1 ? 0 : (int)(threadIdx.x >> 6) * kWords);  // widths 3, 4: CAP tiles
   uint16_t* sm = (uint16_t*)(st + CAP);        // CAP (or CAP/2) meta words
@@ -849,9 +872,13 @@ __global__ __launch_bounds__(64 * WPG, (batch_waves_per_simd<CAP, NPL>())) void 
     bool ok = true;
     if (width == 4) {
       if (lane < cnt) {
-        st[lane] = t;
-        // the 64-node round's stack has its own meta layout
-        sm[lane] = NPL == 64 ? (uint16_t)meta4_in(m) : m;
+        // the 64-node round's stack has its own layout
+        if constexpr (NPL == 64) {
+          e4_put<CAP>(st, lane, t, meta4_in(m));
+        } else {
+          st[lane] = t;
+          sm[lane] = m;
+        }
       }
       WAVE_SYNC();
       ok = A.first_solution
@@ -1196,7 +1223,8 @@ static int occupancy_t() {
 // Supported (stack capacity, nodes per round, waves per workgroup) triples.
 #define BATCH_CONFIGS(X)                                                                         \
   X(128, 16, 1) X(256, 16, 1) X(512, 16, 1) X(1024, 16, 1) X(2048, 16, 1) X(256, 64, 1)          \
-  X(512, 64, 1) X(640, 64, 1) X(768, 64, 1) X(1024, 64, 1) X(2048, 64, 1) X(512, 64, 2) X(1024, 64, 2) X(2048, 64, 2)        \
+  X(512, 64, 1) X(640, 64, 1) X(672, 64, 1) X(768, 64, 1) X(1024, 64, 1) X(2048, 64, 1)    \
+  X(512, 64, 2) X(1024, 64, 2) X(2048, 64, 2)                                                     \
   X(512, 64, 4) X(1024, 64, 4) X(2048, 64, 4)
 
 hipError_t launch_batch4(int lds_cap, int npl, int wpg, int grid, const BatchArgs& A, hipStream_t s) {

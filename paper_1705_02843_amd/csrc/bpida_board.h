@@ -252,6 +252,73 @@ constexpr bool check_meta4() {
 }
 static_assert(check_meta4(), "width-4 stack meta does not round-trip");
 
+// Width-4 stacks of 64-node rounds come in two layouts.  Split (most sizes):
+// CAP 8-byte states, then CAP 2-byte meta words, 10 bytes an entry.
+// Interleaved (672 entries): entry i holds its state at bytes
+// 12i .. 12i + 7 (two dwords) and its meta word at 12i + 8, so that one
+// address serves both (one instruction less per child and per node, 20 %
+// more LDS per entry, i.e. fewer waves per compute unit at a given size).
+// st is the stack's base.
+template <int CAP>
+constexpr bool stack4_interleaved() {
+  return CAP == 672;
+}
+template <int CAP>
+constexpr uint32_t stack4_bytes() {
+  return (stack4_interleaved<CAP>() ? 12u : 10u) * (uint32_t)CAP;
+}
+constexpr uint32_t kEntry4 = 12;
+template <int CAP>
+__device__ __forceinline__ uint64_t e4_tile(const uint64_t* st, uint32_t i) {
+  if constexpr (stack4_interleaved<CAP>()) {
+    const uint32_t* p = (const uint32_t*)((const char*)st + kEntry4 * i);
+    return (uint64_t)p[0] | ((uint64_t)p[1] << 32);
+  } else {
+    return st[i];
+  }
+}
+template <int CAP>
+__device__ __forceinline__ uint32_t e4_meta(const uint64_t* st, uint32_t i) {
+  if constexpr (stack4_interleaved<CAP>()) return *(const uint16_t*)((const char*)st + kEntry4 * i + 8);
+  else return ((const uint16_t*)(st + CAP))[i];
+}
+template <int CAP>
+__device__ __forceinline__ void e4_put(uint64_t* st, uint32_t i, uint64_t t, uint32_t m) {
+  if constexpr (stack4_interleaved<CAP>()) {
+    uint32_t* p = (uint32_t*)((char*)st + kEntry4 * i);
+    p[0] = (uint32_t)t;
+    p[1] = (uint32_t)(t >> 32);
+    *(uint16_t*)(p + 2) = (uint16_t)m;
+  } else {
+    st[i] = t;
+    ((uint16_t*)(st + CAP))[i] = (uint16_t)m;
+  }
+}
+
+// Moves width-4 stack entries [src, src + n) down to [dst, dst + n), dst <
+// src, 64 at a time in ascending order: every entry is read before anything
+// is written over it.
+template <int CAP>
+__device__ __forceinline__ void move_down4(uint64_t* st, uint32_t dst, uint32_t src, uint32_t n) {
+  const uint32_t lane = (uint32_t)lane_id();
+  for (uint32_t i = 0; i < n; i += 64u) {
+    const uint32_t k = i + lane;
+    if (k < n) {
+      const uint64_t t = e4_tile<CAP>(st, src + k);
+      const uint32_t m = e4_meta<CAP>(st, src + k);
+      e4_put<CAP>(st, dst + k, t, m);
+    }
+  }
+  WAVE_SYNC();
+}
+
+// r * 12 + c in one instruction (r below 2^24).
+__device__ __forceinline__ uint32_t mad12(uint32_t r, uint32_t c) {
+  uint32_t d;
+  asm("v_mad_u32_u24 %0, %1, 12, %2" : "=v"(d) : "v"(r), "s"(c));
+  return d;
+}
+
 // Move A of the width-4 round takes tile t away from its goal cell (tile t's
 // goal cell is t): the coordinate that changes is the row for U and D, the
 // column for L and R, and the tile moves away when its goal coordinate lies
@@ -423,29 +490,41 @@ __device__ __forceinline__ void bp_move4(uint64_t* st, uint32_t& out, const uint
   }
   const uint32_t r =
       __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
-  // byte offsets into the stack: entry out + r (below CAP: the caller leaves
-  // room for the largest round).  The two stores run under the keep mask
-  // with no branch around them (the meta array follows the CAP tiles); the
+  // entry out + r (below CAP: the caller leaves room for the largest round).
+  // The stores run under the keep mask with no branch around them; the
   // compiler would put a skip jump around stores in a divergent branch, so
-  // this asm sets EXEC to the mask, stores and restores EXEC itself.
-  const uint32_t pst = (r + out) << 3;
-  const uint32_t as = lds_addr(st) + pst;
-  const uint32_t am = lds_addr(st) + (pst >> 2);
+  // the asm sets EXEC to the mask, stores and restores EXEC itself.
   uint64_t saved;
-  asm volatile(
-      "s_and_saveexec_b64 %0, %1\n\t"
-      "ds_write_b64 %2, %3\n\t"
-      "ds_write_b16 %4, %5 offset:%6\n\t"
-      "s_mov_b64 exec, %0"
-      : "=&s"(saved)
-      : "s"(km), "v"(as), "v"(cs), "v"(am), "v"(cm), "i"(CAP * 8)
-      : "memory", "scc");
+  if constexpr (stack4_interleaved<CAP>()) {
+    const uint32_t as = lds_addr(st) + mad12(r, out * kEntry4);
+    asm volatile(
+        "s_and_saveexec_b64 %0, %1\n\t"
+        "ds_write2_b32 %2, %3, %4 offset1:1\n\t"
+        "ds_write_b16 %2, %5 offset:8\n\t"
+        "s_mov_b64 exec, %0"
+        : "=&s"(saved)
+        : "s"(km), "v"(as), "v"((uint32_t)cs), "v"((uint32_t)(cs >> 32)), "v"(cm)
+        : "memory", "scc");
+  } else {
+    // (the meta array follows the CAP states)
+    const uint32_t pst = (r + out) << 3;
+    const uint32_t as = lds_addr(st) + pst;
+    const uint32_t am = lds_addr(st) + (pst >> 2);
+    asm volatile(
+        "s_and_saveexec_b64 %0, %1\n\t"
+        "ds_write_b64 %2, %3\n\t"
+        "ds_write_b16 %4, %5 offset:%6\n\t"
+        "s_mov_b64 exec, %0"
+        : "=&s"(saved)
+        : "s"(km), "v"(as), "v"(cs), "v"(am), "v"(cm), "i"(CAP * 8)
+        : "memory", "scc");
+  }
   out += (uint32_t)__popcll(km);
 }
 
 // One BPDFS round of the width-4 board with one popped node per lane: pops
-// kp = min(64, top) nodes from a stack of entries [0, top) (CAP tiles, then
-// CAP meta words in the width-4 layout), tests them for the goal and pushes
+// kp = min(64, top) nodes from a stack of entries [0, top) (either layout
+// above, meta words in the width-4 layout), tests them for the goal and pushes
 // every legal, non-undoing child with f <= limit.  The caller guarantees
 // that the children fit, top + 2*kp <= CAP; FULL: kp = 64 and `goals` is a
 // 64-bit mask that collects the lanes that expanded a goal, else a count.
@@ -457,9 +536,18 @@ __device__ __forceinline__ uint32_t bp_round64_4(uint64_t* st, uint32_t top, int
                                                  const RoundConsts4& rk) {
   const int lane = lane_id();
   const uint32_t base = top - (uint32_t)kp;
-  const uint32_t pst = opaque((base + (uint32_t)lane) << 3);
-  const uint64_t s = *(const uint64_t*)((const char*)st + pst);
-  const uint32_t m = *(const uint16_t*)((const char*)(st + CAP) + (pst >> 2));
+  uint64_t s;
+  uint32_t m;
+  if constexpr (stack4_interleaved<CAP>()) {
+    const uint32_t pe = opaque(mad12((uint32_t)lane, base * kEntry4));
+    const uint32_t* pp = (const uint32_t*)((const char*)st + pe);
+    s = (uint64_t)pp[0] | ((uint64_t)pp[1] << 32);
+    m = *(const uint16_t*)(pp + 2);
+  } else {
+    const uint32_t pst = opaque((base + (uint32_t)lane) << 3);
+    s = *(const uint64_t*)((const char*)st + pst);
+    m = *(const uint16_t*)((const char*)(st + CAP) + (pst >> 2));
+  }
   const uint64_t actm = FULL || kp >= 64 ? ~0ull : ((1ull << kp) - 1ull);
   const uint64_t gm = __builtin_amdgcn_uicmpl(s, rk.goal, 32);
   if constexpr (FULL) goals |= gm;

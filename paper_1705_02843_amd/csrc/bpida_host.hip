@@ -1210,8 +1210,8 @@ extern "C" int bpida_set_option(const char* key, int64_t value) {
     if (value < -1 || value > kMaxDepth) return BPIDA_EINVAL;
     g_opt.frontier_depth = value;
   } else if (k == "lds_stack_capacity") {
-    if (value != -1 && value != 128 && value != 256 && value != 512 && value != 640 && value != 768 && value != 1024 &&
-        value != 2048)
+    if (value != -1 && value != 128 && value != 256 && value != 512 && value != 640 &&
+        value != 672 && value != 768 && value != 1024 && value != 2048)
       return BPIDA_EINVAL;
     g_opt.lds_stack_capacity = value;
   } else if (k == "nodes_per_round") {

@@ -324,11 +324,9 @@ __global__ __launch_bounds__(64) void search64_kernel(const Node* __restrict__ r
                                                       int32_t* __restrict__ stop,
                                                       uint32_t* __restrict__ load) {
   static_assert((CAP & (CAP - 1)) == 0 && CAP >= 512, "stack size for 64-node rounds");
-  // one array: CAP tiles, then CAP meta words (the layout the batched
-  // kernel's stacks have, sm == st + CAP)
-  __shared__ __attribute__((aligned(16))) uint64_t lds[(10 * CAP) / 8];
+  // the width-4 round's stack (its layout for this size)
+  __shared__ __attribute__((aligned(16))) uint64_t lds[stack4_bytes<CAP>() / 8];
   uint64_t* st = lds;
-  uint16_t* sm = (uint16_t*)(lds + CAP);
   constexpr uint32_t kCap = CAP;
   // largest growth of one round: at most 3 children a node (a unit starts
   // from one root, whose round cannot overflow)
@@ -358,11 +356,8 @@ __global__ __launch_bounds__(64) void search64_kernel(const Node* __restrict__ r
       fmin = min(fmin, (int)R.f);
       continue;
     }
-    if (lane == 0) {
-      st[0] = R.tiles;
-      // (the width-4 round's stack meta layout)
-      sm[0] = (uint16_t)meta4_in((R.meta & 0xFFu) | ((uint32_t)(limit - (int)R.f) << 8));
-    }
+    // (the width-4 round's meta layout)
+    if (lane == 0) e4_put<CAP>(st, 0, R.tiles, meta4_in((R.meta & 0xFFu) | ((uint32_t)(limit - (int)R.f) << 8)));
     WAVE_SYNC();
     const uint64_t rounds0 = rounds;
     uint32_t top = 1;
@@ -371,19 +366,15 @@ __global__ __launch_bounds__(64) void search64_kernel(const Node* __restrict__ r
       if (top < 64u && sp > 0) {
         // the last spilled chunk comes back below the remaining entries
         uint64_t t = 0;
-        uint16_t m = 0;
+        uint32_t m = 0;
         if ((uint32_t)lane < top) {
-          t = st[lane];
-          m = sm[lane];
+          t = e4_tile<CAP>(st, lane);
+          m = e4_meta<CAP>(st, lane);
         }
         WAVE_SYNC();
-        if ((uint32_t)lane < top) {
-          st[64 + lane] = t;
-          sm[64 + lane] = m;
-        }
+        if ((uint32_t)lane < top) e4_put<CAP>(st, 64 + lane, t, m);
         sp -= 64;
-        st[lane] = sp_t[sp + lane];
-        sm[lane] = sp_m[sp + lane];
+        e4_put<CAP>(st, lane, sp_t[sp + lane], sp_m[sp + lane]);
         top += 64u;
         WAVE_SYNC();
       }
@@ -392,18 +383,18 @@ __global__ __launch_bounds__(64) void search64_kernel(const Node* __restrict__ r
         if (sp + 64 > spill_cap) {
           err = 1;  // entries are dropped; the host reports BPIDA_ENOMEM
         } else {
-          sp_t[sp + lane] = st[lane];
-          sp_m[sp + lane] = sm[lane];
+          sp_t[sp + lane] = e4_tile<CAP>(st, lane);
+          sp_m[sp + lane] = (uint16_t)e4_meta<CAP>(st, lane);
           sp += 64;
           spilled += 64;
           spill_hw = max(spill_hw, sp);
         }
         WAVE_SYNC();
-        move_down(st, sm, 0u, 64u, top - 64u);
+        move_down4<CAP>(st, 0u, 64u, top - 64u);
         top -= 64u;
       }
       const int kp = (int)min(top, 64u);
-      top = bp_round64w<4, CAP, true, false>(st, sm, top, kp, goals, rk);
+      top = bp_round64_4<CAP, false>(st, top, kp, goals, rk);
       expanded += (uint64_t)kp;
       rounds += 1;
       if (!stop) {
@@ -413,7 +404,7 @@ __global__ __launch_bounds__(64) void search64_kernel(const Node* __restrict__ r
         uint64_t gm = 0;  // lanes that expanded a goal (only "any" matters)
         uint32_t n = 0;
         while (top - 64u <= kCap - kGrow - 64u) {
-          top = bp_round64w<4, CAP, true, true>(st, sm, top, 64, gm, rk);
+          top = bp_round64_4<CAP, true>(st, top, 64, gm, rk);
           ++n;
         }
         if (gm != 0) goals += 1;

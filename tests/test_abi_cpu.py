@@ -96,12 +96,12 @@ def test_options_roundtrip_and_validation(B):
             B.set_option(k, v)
     assert B.get_option("no_such_key") == -(2 ** 63)
     assert B.get_option("donate_every") == 128 and B.get_option("donate_min") == -1
-    # the two non-power-of-two stacks of the batched 64-node round
+    # the non-power-of-two stacks of the batched 64-node round
     old_cap = B.get_option("lds_stack_capacity")
-    for cap in (640, 768):
+    for cap in (640, 672, 768):
         B.set_option("lds_stack_capacity", cap)
         assert B.get_option("lds_stack_capacity") == cap
-    for cap in (639, 700, 896):
+    for cap in (560, 639, 700, 896):
         with pytest.raises(B.BpidaError):
             B.set_option("lds_stack_capacity", cap)
     B.set_option("lds_stack_capacity", old_cap)

@@ -124,7 +124,7 @@ def test_split_depths_agree(opts, depth, mode):
 
 CAPS = [("plain", 128), ("plain", 1024), ("plain64", 512), ("plain64", 2048),
         ("batched16", 128), ("batched16", 256), ("batched16", 2048), ("batched", 512),
-        ("batched", 640), ("batched", 768), ("batched", 1024), ("batched", 2048)]
+        ("batched", 640), ("batched", 672), ("batched", 768), ("batched", 1024), ("batched", 2048)]
 
 
 @pytest.mark.parametrize("mode,cap", CAPS)
@@ -312,7 +312,8 @@ def test_lost_work_fails_fast(opts):
 
 
 @pytest.mark.parametrize("mode,wg,cap", [("batched", 64, -1), ("batched16", 64, -1), ("batched", 128, -1),
-                                         ("batched", 256, -1), ("batched", 64, 640), ("batched", 64, 768)])
+                                         ("batched", 256, -1), ("batched", 64, 640), ("batched", 64, 672),
+                                         ("batched", 64, 768)])
 def test_c3_4096_batched_exact_where_stored_and_valid_everywhere(opts, mode, wg, cap):
     """The 4096-state uneven workload in one persistent launch (the grid is
     smaller than the batch): exact against the stored oracle results, and

@@ -182,6 +182,36 @@ def test_c4_4x4_part_with_16_node_rounds_exact(B):
         assert list(nodes[i, :m]) == r["nodes"] and not nodes[i, m:].any(), i
 
 
+def test_c4_3x3_and_4x4_parts_on_the_interleaved_stack(B):
+    """The 3x3 and 4x4 parts of the mixed workload in one launch on 672-entry
+    stacks, where the 4x4 stack interleaves each entry's state and meta word
+    and the 3x3 stack shares its LDS: exact against the stored oracle
+    results of both widths."""
+    from paper_1705_02843_amd import instances as I
+    g3, g4 = _golden("c4_mixed_w3"), _golden("c4_mixed_w4")
+    if g3 is None or g4 is None:
+        pytest.skip("no stored results for the 3x3 and 4x4 parts")
+    print("case: c4 3x3 + 4x4 parts, one launch, 672-entry stacks", flush=True)
+    d = I.c4_mixed()
+    s3, s4 = d[3][0], d[4][0]
+    old = {k: B.get_option(k) for k in ("mode", "nodes_per_round", "lds_stack_capacity", "wg_size")}
+    B.set_option("mode", 1)
+    B.set_option("nodes_per_round", 64)
+    B.set_option("wg_size", 64)
+    B.set_option("lds_stack_capacity", 672)
+    try:
+        rc, ln, nodes = B.solve_mixed_raw(list(s3) + list(s4))
+    finally:
+        for k, v in old.items():
+            B.set_option(k, v)
+    assert rc == B.OK, B.strerror(rc)
+    for off, g in ((0, g3), (len(s3), g4)):
+        for i, r in enumerate(g["instances"]):
+            m = len(r["nodes"])
+            assert ln[off + i] == r["length"], (off, i)
+            assert list(nodes[off + i, :m]) == r["nodes"] and not nodes[off + i, m:].any(), (off, i)
+
+
 def test_mixed_batch_with_bad_states(B):
     """Invalid and unsolvable boards of every width inside one mixed batch:
     each gets its own status (-1 length, zero counts), the first failing code
