@@ -535,7 +535,8 @@ __device__ void admitter_loop(const BatchArgs& A, uint64_t* st, uint16_t* sm, ui
                                      const_cast<int32_t*>(A.goal_g) + slot);
       S.root_off += r0;
       S.nroots = V.walks[walk_row(I.blank, 4) + V.depth];
-      if (S.limit > A.max_limit) S.done = -3;  // BPIDA_ELIMIT
+      // a first limit past the cap or past the 64 output columns
+      if (S.limit > A.max_limit || S.col >= 64) S.done = -3;  // BPIDA_ELIMIT
     }
     if (lane == 0) A.is[slot] = S;
     WAVE_SYNC_MEM();

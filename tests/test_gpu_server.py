@@ -130,6 +130,31 @@ def test_full_ring_reports_eagain_and_recovers(B):
     assert r2[0] == l1[5] and (r2[1] == n1[5]).all()
 
 
+def test_first_limit_past_the_output_columns_answers_elimit(B):
+    """A first limit whose output column is past the 64 per request (a start
+    threshold far above h0) is answered BPIDA_ELIMIT with no counts, as the
+    batched solve answers it, and the server keeps serving."""
+    print("case: server with start_threshold 250, 4 c1 states", flush=True)
+    s1, l1, n1 = load_golden("c1_walk40")
+    old = B.get_option("start_threshold")
+    B.set_option("start_threshold", 250)
+    try:
+        with B.Server(max_inflight=16, ring_capacity=64) as srv:
+            pending = {srv.submit(s1[i]): i for i in range(4)}
+            assert None not in pending
+            got = {}
+            drain(srv, pending, got, time.time() + 60)
+            assert srv.stop() == B.OK
+        rc, ln, _ = B.solve_raw(s1[:4])
+    finally:
+        B.set_option("start_threshold", old)
+    assert len(got) == 4
+    for i in range(4):
+        length, nodes, status = got[i]
+        assert status == B.ELIMIT and length == -1 and not nodes.any(), (i, status, length)
+    assert rc == B.ELIMIT and (ln == -1).all()
+
+
 def test_queue_overflow_answers_enomem_never_wrong_counts(B):
     print("case: server with a 64-slot queue, a 1-poll push wait and one searching "
           "workgroup, 64 + 12 golden states", flush=True)
