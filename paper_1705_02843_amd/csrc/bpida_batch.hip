@@ -596,8 +596,9 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
   // 64-node rounds on 3x3 and 4x4 stacks store without branches (under the
   // keep mask)
   constexpr bool kMasked = NPL == 64 && sizeof(S) == 8;
-  // the width-4 64-node round keeps its stack in its own layout (12-byte
-  // entries, its own meta word); chunks carry the common meta word
+  // the width-4 64-node round keeps its stack in its own layout (its own
+  // meta word; 12-byte interleaved entries at 672 entries); chunks carry
+  // the common meta word
   constexpr bool kMeta4 = NPL == 64 && W == 4;
   constexpr int kCap = CAP;
   const LaneMap M = make_lane_map(lane);

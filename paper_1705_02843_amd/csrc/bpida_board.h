@@ -575,12 +575,13 @@ __device__ __forceinline__ uint32_t bp_round64_4(uint64_t* st, uint32_t top, int
   return out;
 }
 
-// Per-node values shared by the four moves of a 64-node round.
+// Per-node values shared by the four moves of a 64-node round (widths 3
+// and 5).
 struct NodeCtx {
   uint32_t b;      // blank cell
-  uint32_t shb;    // BITS * b (width 4: in the low six bits only)
+  uint32_t shb;    // BITS * b
   uint32_t rowi;   // vertical moves: the blank's row (table index part)
-  uint32_t coli;   // horizontal moves: the blank's column (x W for width 4)
+  uint32_t coli;   // horizontal moves: the blank's column
   uint32_t lmx;    // bit (A + 4 up): move A survives the f test
   uint32_t mbase;  // slack << 8 | blank
 };
