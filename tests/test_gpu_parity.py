@@ -33,7 +33,8 @@ def B():
 OPTION_KEYS = ("mode", "frontier_depth", "lds_stack_capacity", "spill_capacity",
                "max_workgroups", "max_threshold", "queue_capacity", "watchdog_ms",
                "nodes_per_round", "budget_ms", "first_solution", "static_lb", "start_threshold",
-               "seed_chunk", "plain_nodes_per_round", "push_spin", "wg_size")
+               "seed_chunk", "plain_nodes_per_round", "push_spin", "wg_size", "donate_every",
+               "donate_min")
 # plain: one launch per instance and limit, 16-node rounds (Alg. 1's map);
 # plain64: the same with 64-node rounds; batched: persistent launch, 64-node
 # rounds; batched16: persistent, 16-node rounds (tracks pruned f, so every
@@ -142,6 +143,27 @@ def test_lds_capacity_and_spill_agree(opts, cap, mode):
     assert_parity(ln, nodes, want_len, want_nodes, "cap=%d" % cap)
     if cap == 128 or (mode in ("batched", "plain64") and cap == 512):
         assert B.last_stats()["spilled"] > 0  # the spill path was exercised
+
+
+@pytest.mark.parametrize("cap", [640, 672, 1024])
+def test_aggressive_donation_exact(opts, cap):
+    """Donation at every 64-round poll from any stack of two or more entries
+    (the smallest interval and threshold the options allow), on the split
+    (640, 1024) and interleaved (672) width-4 stacks: every donated half
+    moves through the stack's own layout and back; exact against the stored
+    oracle results, with donations counted."""
+    B = opts
+    _say("case: c2 first 30, donate_every 64, donate_min 2, stack %d" % cap)
+    set_mode(B, "batched")
+    B.set_option("lds_stack_capacity", cap)
+    B.set_option("donate_every", 64)
+    B.set_option("donate_min", 2)
+    states, want_len, want_nodes = load_golden("c2_md30_38")
+    states, want_len, want_nodes = states[:30], want_len[:30], want_nodes[:30]
+    rc, ln, nodes = B.solve_raw(states)
+    assert rc == B.OK, B.strerror(rc)
+    assert_parity(ln, nodes, want_len, want_nodes, "cap=%d" % cap)
+    assert B.last_stats()["donations_voluntary"] > 0
 
 
 @pytest.mark.parametrize("mode", sorted(MODES))
