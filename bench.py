@@ -425,7 +425,8 @@ def main():
     if cap < 0:
         cap = 1024 if npl == 64 else 512
     if args.mode == "batched":
-        kname = "batch4_kernel<%d, %d, %d>" % (cap, npl, bpida.get_option("wg_size") // 64)
+        kname = "batch4_kernel<%d, %d, %d, %s>" % (cap, npl, bpida.get_option("wg_size") // 64,
+                                                    "true" if bpida.get_option("first_solution") else "false")
     else:
         pn = bpida.get_option("plain_nodes_per_round")
         kname = ("search64_kernel<%d>" if pn == 64 else "search4_kernel<%d>") % cap

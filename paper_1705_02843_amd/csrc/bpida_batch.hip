@@ -727,12 +727,14 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
       if (poll && (tick & 63u) == 0 && wave_bcast(lane == 0 ? ld_relaxed(&A.is[inst].stop) : 0))
         break;
     }
-    if constexpr (NPL == 64 && !FS) {
+    if constexpr (NPL == 64) {
       // Full rounds with nothing else to test: while the stack holds 64
       // entries and has room for their children (the condition under which
       // the round above needs no spill) and no poll is due, 64-node rounds
-      // run back to back; their counts are added once at the end.  (The
-      // first-solution search keeps its per-round goal test above.)
+      // run back to back; their counts are added once at the end.  The
+      // first-solution search also leaves after a round that expanded a goal
+      // (a test of the wave's goal mask, uniform), and stops its instance
+      // outside the loop.
       const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane((int)(poll_mask - (tick & poll_mask)));
       uint32_t r = 0;
       uint64_t gm = 0;  // lanes that expanded a goal (only "any" matters)
@@ -741,11 +743,20 @@ __device__ bool run_unit(const BatchArgs& A, int inst, int limit, typename Board
         if (top - 64u > (uint32_t)(kCap - kGrow - 64)) break;
         top = bp_round64w<W, CAP, kMasked, true>(st, sm, top, 64, gm, rk);
         ++r;
+        if constexpr (FS) {
+          if (gm != 0) break;
+        }
       }
       if (gm != 0) goals += 1;
       tick += r;
       expanded += 64ull * r;
       wc.rounds += r;
+      if constexpr (FS) {
+        if (goals > 0) {
+          if (lane == 0) __hip_atomic_store(&A.is[inst].stop, 1, __ATOMIC_RELAXED, AGENT);
+          break;
+        }
+      }
     }
   }
   // 64-node rounds: a pruned child always has f = limit + 2 (bp_round64w),
@@ -775,7 +786,7 @@ constexpr int batch_waves_per_simd() {
   return w > 6 ? 6 : w < 1 ? 1 : w;
 }
 
-template <int CAP, int NPL, int WPG>
+template <int CAP, int NPL, int WPG, bool FS>
 __global__ __launch_bounds__(64 * WPG, (batch_waves_per_simd<CAP, NPL>())) void batch4_kernel(BatchArgs A) {
   static_assert(CAP % 16 == 0 && (NPL == 64 || (CAP & (CAP - 1)) == 0), "stack size");
   static_assert(NPL == 16 || NPL == 64, "nodes per round");
@@ -883,11 +894,8 @@ __global__ __launch_bounds__(64 * WPG, (batch_waves_per_simd<CAP, NPL>())) void 
         }
       }
       WAVE_SYNC();
-      ok = A.first_solution
-               ? run_unit<4, CAP, NPL, true>(A, inst, limit, st, sm, cnt, wc, tick, deadline,
-                                             expanded, goals, fmin)
-               : run_unit<4, CAP, NPL, false>(A, inst, limit, st, sm, cnt, wc, tick, deadline,
-                                              expanded, goals, fmin);
+      ok = run_unit<4, CAP, NPL, FS>(A, inst, limit, st, sm, cnt, wc, tick, deadline,
+                                             expanded, goals, fmin);
     } else if (width == 3) {
       if constexpr (CAP >= 256) {
         if (lane < cnt) {
@@ -895,11 +903,8 @@ __global__ __launch_bounds__(64 * WPG, (batch_waves_per_simd<CAP, NPL>())) void 
           sm[lane] = m;
         }
         WAVE_SYNC();
-        ok = A.first_solution
-                 ? run_unit<3, CAP, 64, true>(A, inst, limit, st, sm, cnt, wc, tick, deadline,
-                                              expanded, goals, fmin)
-                 : run_unit<3, CAP, 64, false>(A, inst, limit, st, sm, cnt, wc, tick, deadline,
-                                               expanded, goals, fmin);
+        ok = run_unit<3, CAP, 64, FS>(A, inst, limit, st, sm, cnt, wc, tick, deadline,
+                                              expanded, goals, fmin);
       }
     } else {
       if constexpr (CAP / 2 >= 256) {
@@ -908,11 +913,8 @@ __global__ __launch_bounds__(64 * WPG, (batch_waves_per_simd<CAP, NPL>())) void 
           sm[lane] = m;
         }
         WAVE_SYNC();
-        ok = A.first_solution
-                 ? run_unit<5, CAP / 2, 64, true>(A, inst, limit, st5, sm, cnt, wc, tick,
-                                                  deadline, expanded, goals, fmin)
-                 : run_unit<5, CAP / 2, 64, false>(A, inst, limit, st5, sm, cnt, wc, tick,
-                                                   deadline, expanded, goals, fmin);
+        ok = run_unit<5, CAP / 2, 64, FS>(A, inst, limit, st5, sm, cnt, wc, tick,
+                                                  deadline, expanded, goals, fmin);
       }
     }
     if (!ok) break;
@@ -1207,19 +1209,26 @@ hipError_t launch_batch_status(const InstState* d_is, int n, const QueueCtl* d_q
   return hipGetLastError();
 }
 
+// The first-solution search is a kernel of its own: with both unit loops in
+// one kernel the register allocation of each suffers.
 template <int CAP, int NPL, int WPG>
 static hipError_t launch_batch_t(int grid, const BatchArgs& A, hipStream_t s) {
-  hipLaunchKernelGGL((batch4_kernel<CAP, NPL, WPG>), dim3(grid), dim3(64 * WPG), 0, s, A);
+  if (A.first_solution)
+    hipLaunchKernelGGL((batch4_kernel<CAP, NPL, WPG, true>), dim3(grid), dim3(64 * WPG), 0, s, A);
+  else
+    hipLaunchKernelGGL((batch4_kernel<CAP, NPL, WPG, false>), dim3(grid), dim3(64 * WPG), 0, s, A);
   return hipGetLastError();
 }
 
 template <int CAP, int NPL, int WPG>
 static int occupancy_t() {
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch4_kernel<CAP, NPL, WPG>, 64 * WPG, 0) !=
-      hipSuccess)
+  int nb = 0, nf = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch4_kernel<CAP, NPL, WPG, false>, 64 * WPG, 0) !=
+          hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nf, batch4_kernel<CAP, NPL, WPG, true>, 64 * WPG, 0) !=
+          hipSuccess)
     return 0;
-  return nb;
+  return nb < nf ? nb : nf;  // the grid suits either kernel
 }
 
 // Supported (stack capacity, nodes per round, waves per workgroup) triples.
