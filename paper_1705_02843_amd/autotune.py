@@ -9,8 +9,10 @@ Axes: nodes per round with the LDS stack capacity (16: four lanes per node,
 Alg. 1's map; 64: one node per lane), the workgroup size (64, 128 or 256
 threads: 1, 2 or 4 independent waves, Sec. 5's block = one wave, several
 per workgroup), the root split depth D (4..10), the size of the persistent
-grid (the occupancy limit or half of it), and the donation policy (rounds
-between checks, smallest donating stack, entries per donated chunk).  The
+grid (the occupancy limit, or a half, a quarter or an eighth of it), and the
+donation policy (rounds between checks, smallest donating stack, entries per
+donated chunk).  Batch size classes: tiny (up to 64 states), small (256),
+medium (2048), large.  The
 search is coordinate descent: starting from the stored or the library's
 options, each axis in turn is swept with the others fixed and the fastest
 value kept, for two passes over all axes.  Mixed-width workloads are keyed
@@ -32,7 +34,7 @@ KEYS = ("nodes_per_round", "lds_stack_capacity", "wg_size", "frontier_depth", "m
 
 
 def size_class(n: int) -> str:
-    return "small" if n <= 256 else "medium" if n <= 2048 else "large"
+    return "tiny" if n <= 64 else "small" if n <= 256 else "medium" if n <= 2048 else "large"
 
 
 def axes(grid_full: int):
@@ -42,9 +44,9 @@ def axes(grid_full: int):
         ("round", [(16, 512), (64, 512), (64, 640), (64, 672), (64, 768), (64, 1024), (64, 2048)]),
         ("wg_size", [64, 128, 256]),
         ("frontier_depth", [4, 5, 6, 7, 8, 9, 10]),
-        ("max_workgroups", [0, grid_full // 2]),
+        ("max_workgroups", [0, grid_full // 2, grid_full // 4, grid_full // 8]),
         ("donate_every", [64, 128, 256, 512]),
-        ("donate_min", [-1, 128, 256]),
+        ("donate_min", [-1, 16, 32, 64, 128, 256]),
         ("queue_chunk", [16, 32, 64]),
     ]
 
